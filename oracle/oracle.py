@@ -1,0 +1,263 @@
+"""Python driver for the oracle (liboracle.so, built from ka_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the benchmark's
+CPU-baseline leg.  The product package never imports this module.
+
+The oracle follows the paper (Boccagna, arXiv 1710.05155) step by step, one replica at a
+time: Sec. 2.1 rules (a)-(c) for the exchange, Sec. 2.2 for the overlap observables and
+Sec. 3.3 for their word-level (popcount) form.  The numpy helpers below only marshal
+arrays, count occupied sites (plain sums) and pack bits into the canonical export layout.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            from . import build as _b  # type: ignore
+            _b.build()
+        _lib = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        I32 = ctypes.c_int
+        U64 = ctypes.c_uint64
+        _lib.ko_philox_many.argtypes = [I64, P, P, P]
+        _lib.ko_lattice.argtypes = [I32, I32, P, P, P, P]
+        _lib.ko_lattice.restype = I32
+        _lib.ko_rrg.argtypes = [I64, I32, U64, I64, P, P]
+        _lib.ko_rrg.restype = I32
+        _lib.ko_edges.argtypes = [I64, I32, P, P, P]
+        _lib.ko_edges.restype = I64
+        _lib.ko_colour.argtypes = [I64, I32, P, I64, P, P, P]
+        _lib.ko_colour.restype = I32
+        _lib.ko_init_replica.argtypes = [I64, I64, U64, I64, P]
+        _lib.ko_exchange.argtypes = [I32, I32, I32, I32, P, P, I32, P, P]
+        _lib.ko_pass.argtypes = [I64, I32, P, I64, P, P, P, I32, I32, I64, P, P, P]
+        _lib.ko_accept_bit.argtypes = [U64, I64, I32, I64, I64]
+        _lib.ko_accept_bit.restype = I32
+        _lib.ko_run.argtypes = [I64, I32, P, I64, P, P, P, I32, I32, U64, I64, P, I64, I64, P, P]
+        _lib.ko_threads.restype = I32
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------- Philox
+def philox(ctr, key) -> np.ndarray:
+    """Philox4x32-10 (Salmon et al., SC'11) on an (n, 4) array of counters."""
+    lib = load()
+    ctr = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(-1, 4))
+    key = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.empty_like(ctr)
+    lib.ko_philox_many(ctr.shape[0], _p(ctr), _p(key), _p(out))
+    return out
+
+
+# ----------------------------------------------------------------------------- graphs
+@dataclass
+class Graph:
+    N: int
+    z: int
+    adj: np.ndarray    # (N, z) int32
+    eu: np.ndarray     # (E,) int32, canonical edge order
+    ev: np.ndarray
+    ecls: np.ndarray   # (E,) int32 class of each edge
+    C: int
+    kind: str = "graph"
+    d: int = 0
+    L: int = 0
+
+    @property
+    def E(self) -> int:
+        return int(self.eu.shape[0])
+
+
+def lattice(d: int, L: int) -> Graph:
+    """Periodic hypercubic lattice (Sec. 2.1) with the mod-4 coordinate edge classes."""
+    lib = load()
+    N = L ** d
+    z = 2 * d
+    adj = np.empty((N, z), dtype=np.int32)
+    eu = np.empty(N * d, dtype=np.int32)
+    ev = np.empty(N * d, dtype=np.int32)
+    ecls = np.empty(N * d, dtype=np.int32)
+    rc = lib.ko_lattice(d, L, _p(adj), _p(eu), _p(ev), _p(ecls))
+    if rc != 0:
+        raise ValueError(f"oracle: bad lattice d={d} L={L}")
+    return Graph(N, z, adj, eu, ev, ecls, 4 * d, kind="lattice", d=d, L=L)
+
+
+def rrg_adjacency(N: int, z: int, graph_seed: int, max_attempts: int = 1_000_000):
+    """Configuration-model random regular graph with whole-pairing rejection (Sec. 2.1)."""
+    lib = load()
+    adj = np.empty((N, z), dtype=np.int32)
+    used = ctypes.c_int64(0)
+    rc = lib.ko_rrg(N, z, graph_seed, max_attempts, _p(adj), ctypes.byref(used))
+    if rc != 0:
+        raise ValueError(f"oracle: rrg failed rc={rc} (N={N}, z={z})")
+    return adj, int(used.value)
+
+
+def graph_from_adjacency(adj: np.ndarray) -> Graph:
+    """Canonical edges ({u<v}, lexicographic) and greedy distance-2 edge colouring."""
+    lib = load()
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    N, z = adj.shape
+    E = N * z // 2
+    eu = np.empty(E, dtype=np.int32)
+    ev = np.empty(E, dtype=np.int32)
+    got = lib.ko_edges(N, z, _p(adj), _p(eu), _p(ev))
+    if got != E:
+        raise ValueError("oracle: adjacency is not a simple z-regular graph")
+    ecls = np.empty(E, dtype=np.int32)
+    C = lib.ko_colour(N, z, _p(adj), E, _p(eu), _p(ev), _p(ecls))
+    return Graph(N, z, adj, eu, ev, ecls, int(C), kind="graph")
+
+
+def rrg(N: int, z: int, graph_seed: int) -> Graph:
+    adj, _ = rrg_adjacency(N, z, graph_seed)
+    g = graph_from_adjacency(adj)
+    g.kind = "rrg"
+    return g
+
+
+# ----------------------------------------------------------------------------- dynamics
+def k_from_rho(N: int, rho: float) -> int:
+    """Particle number at density rho: floor(rho*N + 1/2) in IEEE double."""
+    return int(math.floor(float(rho) * float(N) + 0.5))
+
+
+def init(g: Graph, K: int, seed: int, replicas) -> np.ndarray:
+    """Initial occupations (nrep, N) uint8: K sites per replica (uniform K-subset)."""
+    lib = load()
+    reps = [int(b) for b in replicas]
+    occ = np.zeros((len(reps), g.N), dtype=np.uint8)
+    for q, b in enumerate(reps):
+        row = np.zeros(g.N, dtype=np.uint8)
+        lib.ko_init_replica(g.N, int(K), seed, b, _p(row))
+        occ[q] = row
+    return occ
+
+
+def exchange(z: int, m: int, ni: int, nj: int, nbr_i, nbr_j, r: int):
+    lib = load()
+    a = np.ascontiguousarray(np.asarray(nbr_i, dtype=np.uint8))
+    b = np.ascontiguousarray(np.asarray(nbr_j, dtype=np.uint8))
+    oi = ctypes.c_int(0)
+    oj = ctypes.c_int(0)
+    lib.ko_exchange(z, m, ni, nj, _p(a), _p(b), r, ctypes.byref(oi), ctypes.byref(oj))
+    return oi.value, oj.value
+
+
+def class_pass(g: Graph, c: int, m: int, occ: np.ndarray, moved: np.ndarray,
+               accept: np.ndarray) -> None:
+    """One pass over class c with explicit acceptance bits accept[(R, E)] (in place)."""
+    lib = load()
+    R = occ.shape[0]
+    assert occ.shape == (R, g.N) and moved.shape == (R, g.N) and accept.shape == (R, g.E)
+    lib.ko_pass(g.N, g.z, _p(g.adj), g.E, _p(g.eu), _p(g.ev), _p(g.ecls), c, m, R,
+                _p(occ), _p(moved), _p(accept))
+
+
+def accept_bit(seed: int, t: int, c: int, e: int, b: int) -> int:
+    return int(load().ko_accept_bit(seed, t, c, e, b))
+
+
+def run(g: Graph, m: int, seed: int, replicas, occ: np.ndarray, moved: np.ndarray,
+        t0: int, n_sweeps: int) -> None:
+    """Sweeps t0 .. t0+n_sweeps-1 in place on occ/moved (rows = listed replicas)."""
+    lib = load()
+    reps = np.ascontiguousarray(np.asarray(list(replicas), dtype=np.int64))
+    assert occ.shape == (reps.shape[0], g.N) and moved.shape == occ.shape
+    assert occ.flags["C_CONTIGUOUS"] and moved.flags["C_CONTIGUOUS"]
+    lib.ko_run(g.N, g.z, _p(g.adj), g.E, _p(g.eu), _p(g.ev), _p(g.ecls), g.C, m, seed,
+               reps.shape[0], _p(reps), t0, n_sweeps, _p(occ), _p(moved))
+
+
+def threads() -> int:
+    return int(load().ko_threads())
+
+
+# ----------------------------------------------------------------------------- observables
+def observe(occ: np.ndarray, occ0: np.ndarray, moved: np.ndarray):
+    """Per-replica integer counts (Sec. 2.2 overlap q_i = n_i(t) n_i(0); Sec. 3.3):
+    density_b = sum_i n_i, overlap_b = sum_i n_i(t) n_i(0),
+    persistence_b = sum_i n_i(0) (1 - moved_i)  (occupied at t=0 and never vacated)."""
+    o = occ.astype(np.int64)
+    o0 = occ0.astype(np.int64)
+    mv = moved.astype(np.int64)
+    density = o.sum(axis=1)
+    overlap = (o * o0).sum(axis=1)
+    persistence = (o0 * (1 - mv)).sum(axis=1)
+    return density, overlap, persistence
+
+
+def derived(N: int, K: int, overlap: np.ndarray, persistence: np.ndarray):
+    """Replica averages: C = mean_b q_b with q_b = (overlap_b/N - rho^2)/(rho(1-rho))
+    (Sec. 2.2, with the 1/N that makes q(0)=1), chi4 = N (mean q^2 - (mean q)^2), and
+    the mean persistence fraction P = mean_b persistence_b / K."""
+    rho = K / N
+    ov = np.asarray(overlap, dtype=np.float64)
+    if 0 < K < N:
+        q = (ov / N - rho * rho) / (rho * (1.0 - rho))
+        C = float(q.mean())
+        chi4 = float(N * ((q * q).mean() - q.mean() ** 2))
+    else:
+        C, chi4 = float("nan"), float("nan")
+    P = float(np.asarray(persistence, dtype=np.float64).mean() / K) if K > 0 else float("nan")
+    return C, chi4, P
+
+
+def pack(occ: np.ndarray) -> np.ndarray:
+    """Canonical export layout: (R, N) 0/1 -> uint64 (W, N), bit b&63 of word b>>6 is
+    replica b (least significant bit = replica 0 of the word)."""
+    R, N = occ.shape
+    assert R % 64 == 0
+    W = R // 64
+    bits = occ.astype(np.uint64).reshape(W, 64, N)
+    shifts = np.arange(64, dtype=np.uint64).reshape(1, 64, 1)
+    return np.bitwise_or.reduce(bits << shifts, axis=1)
+
+
+def unpack(words: np.ndarray) -> np.ndarray:
+    """Inverse of pack: uint64 (W, N) -> (64W, N) uint8."""
+    W, N = words.shape
+    shifts = np.arange(64, dtype=np.uint64).reshape(1, 64, 1)
+    bits = (words.reshape(W, 1, N) >> shifts) & np.uint64(1)
+    return bits.reshape(W * 64, N).astype(np.uint8)
+
+
+class Sim:
+    """Convenience: a set of replicas of one (graph, m, K, seed) run by the oracle."""
+
+    def __init__(self, g: Graph, m: int, K: int, seed: int, replicas):
+        self.g, self.m, self.K, self.seed = g, m, int(K), seed
+        self.replicas = [int(b) for b in replicas]
+        self.occ = init(g, K, seed, self.replicas)
+        self.occ0 = self.occ.copy()
+        self.moved = np.zeros_like(self.occ)
+        self.t = 0
+
+    def sweep(self, n: int) -> None:
+        if n > 0:
+            run(self.g, self.m, self.seed, self.replicas, self.occ, self.moved, self.t, n)
+            self.t += n
+
+    def observe(self):
+        return observe(self.occ, self.occ0, self.moved)
