@@ -1,0 +1,198 @@
+"""Benchmark of the multispin Kob-Andersen sweep on one MI355X.
+
+Workload (default "cubic128"): 3D cubic lattice L=128 with periodic boundaries, z=6, m=3,
+256 replicas (4 uint64 words per site), 10^4 sweeps per job, overlap and persistence
+observed on a 38-point log-spaced grid (0 and the distinct floor(10^(k/10)) <= 10^4).  One
+step is one whole job: initial state (uniform K-subset per replica) + all sweeps + all
+observations, with rho cycling through 0.80, 0.85, 0.88.  Inputs are synthetic (the
+dynamics needs no data); the lattice and all state are resident on the GPU during the
+timed region.
+
+Metric: site-replica move attempts per second = N * R * sweeps * steps / wall time (one
+sweep attempts every edge once per replica, N attempts per replica in the paper's time
+unit).  Also reported: the roofline of the dominant kernel (the global-memory class pass),
+from HIP-event durations of sampled launches inside the timed region, and the oracle's rate
+on a bounded sample on this host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload cubic128]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "cubic128": dict(kind="lattice", d=3, L=128, m=3, rhos=[0.80, 0.85, 0.88], R=256, sweeps=10_000,
+                     desc="3D cubic lattice L=128 periodic, z=6, m=3, rho in {0.80,0.85,0.88}, 256 replicas "
+                          "(4 uint64 words/site), 10^4 sweeps, overlap+persistence on a 38-point log grid"),
+    "square64": dict(kind="lattice", d=2, L=64, m=2, rhos=[0.70], R=64, sweeps=1000, obs_every=10,
+                     desc="2D square lattice L=64 periodic, z=4, m=2, rho=0.70, 64 replicas, 1000 sweeps, "
+                          "observables every 10 sweeps"),
+    "rrg20": dict(kind="rrg", N=1 << 20, z=4, m=2, rhos=[0.50, 0.55, 0.60, 0.65, 0.70, 0.75], R=64,
+                  sweeps=10_000, graph_seed=1,
+                  desc="random regular graph N=2^20, z=4, m=2, rho 0.50-0.75, 64 replicas, 10^4 sweeps"),
+    "cubic256": dict(kind="lattice", d=3, L=256, m=3, rhos=[0.85], R=256, sweeps=200,
+                     desc="3D cubic lattice L=256 periodic, z=6, m=3, rho=0.85, 256 replicas, 200 sweeps "
+                          "(state beyond the 256 MiB Infinity Cache)"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def class_pass_bytes(w, N, W):
+    """Algorithmic HBM bytes of one global class pass over all words (per-pass model):
+    every site's words are read once as endpoint or neighbour (8 B), the endpoints (half of
+    the sites) are written (8 B) and their moved-ever words read and written (16 B)."""
+    if w["kind"] == "lattice":
+        return N * W * 8 + (N // 2) * W * 8 + (N // 2) * W * 16
+    return None
+
+
+def obs_grid(w):
+    from paper_1710_05155_amd import ka
+    if "obs_every" in w:
+        return list(range(0, w["sweeps"] + 1, w["obs_every"]))
+    return ka.log_time_grid(w["sweeps"])
+
+
+def cpu_baseline(w, seconds_target=15.0):
+    """The oracle (plain scalar C, one replica per thread) on a bounded sample."""
+    from oracle import oracle as o
+    if w["kind"] == "lattice":
+        g = o.lattice(w["d"], w["L"])
+    else:
+        g = o.rrg(w["N"], w["z"], w["graph_seed"])
+    threads = o.threads()
+    rho = w["rhos"][0]
+    K = o.k_from_rho(g.N, rho)
+    reps = list(range(threads))
+    s = o.Sim(g, w["m"], K, 1, reps)
+    t0 = time.perf_counter()
+    s.sweep(1)
+    one = time.perf_counter() - t0
+    n = max(1, int(seconds_target / max(one, 1e-6)) - 1)
+    t0 = time.perf_counter()
+    s.sweep(n)
+    dt = time.perf_counter() - t0
+    total_sweeps = n + 1
+    rate = g.N * len(reps) * total_sweeps / (dt + one)
+    return {"value": rate, "unit": "site-replica move attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(reps)} replicas x {total_sweeps} sweeps of the same lattice at rho={rho} "
+                      f"(one replica per thread), sweeps only"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cubic128", choices=sorted(WORKLOADS))
+    ap.add_argument("--timing-every", type=int, default=16,
+                    help="bracket every k-th class-pass launch with HIP events")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; the replica planes of a job shard across GPUs "
+              "with no communication, but multi-GPU runs are not part of it (use --gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_05155_amd import ka
+
+    w = WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    if w["kind"] == "lattice":
+        g = ka.ka_graph_lattice(w["d"], w["L"])
+    else:
+        g = ka.ka_graph_rrg(w["N"], w["z"], w["graph_seed"])
+    N, R, sweeps = g.N, w["R"], w["sweeps"]
+    W = R // 64
+    grid = obs_grid(w)
+
+    pass_ms_total = 0.0
+    pass_timed = 0
+    pass_launches = 0
+
+    def job(step_idx):
+        rho = w["rhos"][step_idx % len(w["rhos"])]
+        sim = ka.ka_init(g, w["m"], rho, 1, R, stream=stream)
+        if args.timing_every > 0:
+            ka.ka_set_option(sim, ka.KA_OPT_TIMING, args.timing_every)
+        dens, ov, pers = ka.ka_run(sim, grid)
+        K = sim.K
+        assert (dens == K).all(), "particle number not conserved"
+        C, chi4, P = ka.derived_observables(N, K, ov, pers)
+        stats = ka.ka_timing(sim)
+        path = ka.ka_sim_path(sim)
+        sim.free()
+        return rho, C, chi4, P, stats, path
+
+    for k in range(args.warmup):
+        rho, C, chi4, P, _, _ = job(k)
+        log(f"warmup {k}: rho={rho} C(t_max)={C[-1]:.4f} P(t_max)={P[-1]:.4f}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    path = None
+    for k in range(args.steps):
+        rho, C, chi4, P, (launches, timed, ms), path = job(args.warmup + k)
+        pass_launches += launches
+        pass_timed += timed
+        pass_ms_total += ms
+        log(f"step {k}: rho={rho} C(t_max)={C[-1]:.4f} chi4_max={max(chi4[1:]):.3f} P(t_max)={P[-1]:.4f} "
+            f"passes={launches} timed={timed}")
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+
+    attempts = N * R * sweeps * args.steps
+    value = attempts / wall
+    edges = (N * g.z // 2)
+    result = {
+        "metric": "site-replica move attempts/s (1 GPU)",
+        "value": value,
+        "unit": "site-replica move attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1000.0 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "sites": N, "replicas": R, "sweeps_per_step": sweeps,
+                   "observations_per_step": len(grid), "path": {1: "global class passes", 2: "LDS-resident"}[path]},
+        "edge_replica_updates_per_s": edges * R * sweeps * args.steps / wall,
+        "stream_event_ms": gpu_ms,
+    }
+    B = class_pass_bytes(w, N, W)
+    if path == 1 and pass_timed > 0 and B:
+        avg_s = pass_ms_total / pass_timed / 1000.0
+        achieved = B / avg_s / 1e9
+        result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                              "kernel": "k_pass_lattice", "avg_launch_us": avg_s * 1e6,
+                              "bytes_per_launch": B, "timed_launches": pass_timed}
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

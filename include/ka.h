@@ -1,0 +1,158 @@
+/*
+ * ka.h -- C ABI of libka, the MI355X (gfx950) multispin Kob-Andersen Monte Carlo library.
+ *
+ * Method: Boccagna, "A Multispin Algorithm for the Kob-Andersen Stochastic Dynamics on
+ * Regular Lattices" (arXiv 1710.05155).  Sec. 2.1 defines the model (hard-core particles
+ * on a periodic hypercubic lattice or a random regular graph, activation number m <= z-1,
+ * a particle at i may hop to an empty neighbour j iff i has at most m occupied neighbours
+ * and j at most m+1); Sec. 3.1 the multispin coding (bit b of a site's word is the
+ * occupation of independent replica b); Sec. 3.2 the bitwise exchange update; Sec. 2.2 and
+ * Sec. 3.3 the overlap observables.
+ *
+ * Schedule (a reading of the paper, which updates one random pair at a time): one sweep
+ * visits the edge classes c = 0..C-1 in order; the edges of one class are pairwise at
+ * graph distance >= 2 and are updated together.  Every edge of the class is attempted
+ * once per replica, accepted with an independent Bernoulli(1/2) bit:
+ *     acceptance bit of replica b, edge e (canonical id), class c, sweep t
+ *       = bit (b & 63) of half ((b >> 6) & 1) of Philox4x32-10(counter (t, c, e, b >> 7),
+ *         key (seed & 0xffffffff, seed >> 32)),  half 0 = out0 | out1 << 32,
+ *                                                half 1 = out2 | out3 << 32.
+ * Classes: lattices 4*mu + ((x_mu + 2*sum_{nu != mu} x_nu) mod 4) for the edge
+ * (x, x + e_mu), whose canonical id is e = i*d + mu with i = sum_nu x_nu L^nu; general
+ * graphs: the greedy distance-2 edge colouring of the canonical edge list (all {u < v},
+ * lexicographic, e = rank).
+ * Initial state of replica b: the K sites with the smallest keys (u_i, i), u_i = half
+ * (b & 1) of Philox4x32-10(counter (0, 0xFFFFFFFF, i, b >> 1), same key): a uniform sample
+ * of the configurations with K particles (Sec. 3.1).
+ *
+ * Conventions
+ *   - Every function returns KA_OK (0) or a negative error code; ka_last_error() gives a
+ *     message for the calling thread.  No C++ exception crosses this boundary.
+ *   - All pointer arguments are HOST pointers unless stated otherwise.  Inputs are copied;
+ *     the caller keeps ownership of its buffers.  The library owns all device memory.
+ *   - A ka_sim is bound to one device (the current one at ka_init) and one HIP stream.  No
+ *     two host threads may use the same ka_sim at once.  ka_graph objects are immutable and
+ *     may be shared and freed once the sims built from them exist.
+ *   - Canonical state export layout: uint64 [W][N], W = n_replicas / 64; bit (b & 63) of
+ *     word [b >> 6][i] is replica b at site i.  The device layout is private.
+ *   - The sweep index t counts sweeps since ka_init; it is part of the random counter, so a
+ *     run split across calls equals the unsplit run.  t must stay below 2^32.
+ */
+#ifndef KA_H
+#define KA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KA_OK 0
+#define KA_EINVAL (-1)  /* invalid argument (sizes, m, rho, replica count, graph)      */
+#define KA_ENOMEM (-2)  /* host or device allocation failed                           */
+#define KA_EDEVICE (-3) /* HIP runtime or kernel error                                */
+#define KA_ESTATE (-4)  /* call not valid in the current state (e.g. t would overflow) */
+
+typedef struct ka_graph ka_graph;
+typedef struct ka_sim ka_sim;
+
+/* Periodic hypercubic lattice Z_L^d (Sec. 2.1), d in {2, 3}, L >= 4, L % 4 == 0, z = 2d,
+ * N = L^d <= 2^30.  Neighbour order in exports: +e_0, -e_0, +e_1, -e_1, ... */
+int ka_graph_lattice(int d, int L, ka_graph **out);
+
+/* Random z-regular simple graph on N vertices (Sec. 2.1, Bollobas' configuration model):
+ * stubs s = 0..N*z-1 (stub s belongs to vertex s / z) are shuffled by Fisher-Yates
+ * (k = S-1 down to 1, swap k with a uniform j in [0, k]) and positions (2q, 2q+1) paired;
+ * a pairing with a self-loop or a repeated edge is rejected whole and attempt a+1 drawn.
+ * 32-bit word s of attempt a is output s % 4 of Philox4x32-10(counter (a, 0xFFFFFFFE,
+ * s/4 low, s/4 high), key graph_seed); uniform integers by Lemire's multiply-shift
+ * rejection method.  z in [3, 6], z < N, N*z even, N <= 2^28.  Adjacency rows sorted.
+ * Returns KA_ESTATE if no simple pairing is found within 10^6 attempts. */
+int ka_graph_rrg(int64_t N, int z, uint64_t graph_seed, ka_graph **out);
+
+/* Any simple z-regular graph given as adjacency rows adj[N][z] (copied; z in [3, 6]).
+ * KA_EINVAL if an entry is out of range, a self-loop, repeated, or not symmetric. */
+int ka_graph_from_adjacency(int64_t N, int z, const int32_t *adj, ka_graph **out);
+
+/* Sizes: N sites, degree z, number of edges (N*z/2), number of edge classes C. */
+int ka_graph_info(const ka_graph *g, int64_t *N, int *z, int64_t *n_edges, int *n_classes);
+
+/* Copies (any may be NULL): adj [N][z], and per canonical edge e: its endpoints
+ * edge_u[e] < ... (lattices: edge_u = x, edge_v = x + e_mu) and its class edge_class[e]. */
+int ka_graph_export(const ka_graph *g, int32_t *adj, int32_t *edge_u, int32_t *edge_v,
+                    int32_t *edge_class);
+
+void ka_graph_free(ka_graph *g);
+
+/* Device bytes a sim of this graph with n_replicas replicas allocates (serving admission). */
+int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_bytes);
+
+/* Create a simulation of n_replicas (a positive multiple of 64) independent replicas on the
+ * current HIP device with activation number m (0 <= m <= z-1) and K = floor(rho*N + 1/2)
+ * particles (rho in [0, 1], evaluated in IEEE double), and launch the initial-state
+ * kernels on hip_stream (a hipStream_t; NULL = a stream the library creates and owns).
+ * Returns once the kernels are enqueued; t = 0. */
+int ka_init(const ka_graph *g, int m, double rho, uint64_t seed, int n_replicas,
+            void *hip_stream, ka_sim **out);
+
+/* Same with the particle number given directly (0 <= K <= N). */
+int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int n_replicas,
+              void *hip_stream, ka_sim **out);
+
+/* Enqueue n_sweeps sweeps (t -> t + n_sweeps) on the sim's stream; does not synchronise. */
+int ka_sweep(ka_sim *s, int64_t n_sweeps);
+
+/* Per-replica counts at the current t (Sec. 2.2 overlap q_i(t) = n_i(t) n_i(0), summed
+ * over sites as in Sec. 3.3): density[b] = sum_i n_i, overlap[b] = sum_i n_i(t) n_i(0),
+ * persistence[b] = number of sites occupied at t = 0 whose occupation never changed since.
+ * Each output is int64[n_replicas] (any may be NULL); t receives the sweep index.
+ * Synchronises the sim's stream. */
+int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
+               int64_t *persistence);
+
+/* Run to each of the n_obs non-decreasing absolute sweep indices obs_times[q] (each >= the
+ * current t) and record the counts of ka_observe there into row q of density/overlap/
+ * persistence (int64 [n_obs][n_replicas], any may be NULL).  Observations stay on the
+ * device until one synchronisation at the end. */
+int ka_run(ka_sim *s, const int64_t *obs_times, int n_obs, int64_t *density,
+           int64_t *overlap, int64_t *persistence);
+
+/* Copy the state out / in, canonical layout [W][N] each (any output may be NULL).
+ * ka_set_state requires f to be consistent with the dynamics only for the meaning of
+ * persistence; it is not checked.  Both synchronise the stream. */
+int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, int64_t *t);
+int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, const uint64_t *f,
+                 int64_t t);
+
+/* N, replicas, K, m, current t, number of classes (any may be NULL). */
+int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t *K, int *m,
+                int64_t *t, int *n_classes);
+
+/* Options:
+ *   KA_OPT_PATH:   0 = automatic, 1 = one kernel per class pass over global memory,
+ *                  2 = whole sweep loop inside one workgroup per word plane with the plane in
+ *                      LDS (only if it fits; KA_EINVAL otherwise).  Results are identical.
+ *   KA_OPT_TIMING: k > 0 brackets every k-th class-pass launch with HIP events on the sim's
+ *                  stream (for per-kernel durations, read with ka_timing); 0 = off. */
+#define KA_OPT_PATH 1
+#define KA_OPT_TIMING 2
+int ka_set_option(ka_sim *s, int option, int64_t value);
+
+/* Class-pass launches so far, and among them the number bracketed by events and their
+ * summed duration in milliseconds (synchronises the stream). */
+int ka_timing(ka_sim *s, int64_t *launches, int64_t *timed, double *timed_ms);
+
+/* Path a ka_sweep would take now: 1 = global class passes, 2 = LDS-resident. */
+int ka_sim_path(const ka_sim *s, int *path);
+
+void ka_free(ka_sim *s);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char *ka_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KA_H */

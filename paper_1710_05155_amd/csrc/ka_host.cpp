@@ -1,0 +1,998 @@
+// ka_host.cpp -- host side of libka: graphs, edge classes, device state, kernel dispatch.
+//
+// Method: Boccagna, arXiv 1710.05155 (Sec. 2.1 model and graphs, Sec. 3 multispin
+// algorithm).  The C ABI is declared and documented in include/ka.h.
+#include "ka.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "ka_internal.h"
+
+using ka::u64;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+  return fail(KA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------------------------------
+// Philox4x32-10 on the host (Salmon et al., SC'11), for the random regular graph builder.
+// ------------------------------------------------------------------------------------
+void philox_host(const uint32_t in[4], uint64_t seed, uint32_t out[4])
+{
+  uint32_t c0 = in[0], c1 = in[1], c2 = in[2], c3 = in[3];
+  uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// 32-bit words of one configuration-model attempt, buffered four at a time.
+class WordStream {
+ public:
+  WordStream(uint64_t seed, uint32_t attempt) : seed_(seed), attempt_(attempt) {}
+  uint32_t next()
+  {
+    if (have_ == 0) {
+      const uint32_t ctr[4] = {attempt_, 0xFFFFFFFEu, (uint32_t)block_, (uint32_t)(block_ >> 32)};
+      philox_host(ctr, seed_, buf_);
+      ++block_;
+      have_ = 4;
+    }
+    return buf_[4 - have_--];
+  }
+  // Uniform integer in [0, range) by Lemire's multiply-shift method with rejection.
+  uint32_t below(uint32_t range)
+  {
+    uint64_t prod = (uint64_t)next() * range;
+    uint32_t low = (uint32_t)prod;
+    if (low < range) {
+      const uint32_t thresh = (uint32_t)(0u - range) % range;
+      while (low < thresh) {
+        prod = (uint64_t)next() * range;
+        low = (uint32_t)prod;
+      }
+    }
+    return (uint32_t)(prod >> 32);
+  }
+
+ private:
+  uint64_t seed_;
+  uint32_t attempt_;
+  uint64_t block_ = 0;
+  uint32_t buf_[4];
+  int have_ = 0;
+};
+
+}  // namespace
+
+// ----------------------------------------------------------------------------------------
+// Graph
+// ----------------------------------------------------------------------------------------
+struct ka_graph {
+  int lattice = 0;  // 1: hypercubic lattice (d, L); 0: general z-regular graph
+  int d = 0, L = 0;
+  int64_t N = 0;
+  int z = 0;
+  int C = 0;
+  std::vector<int32_t> adj;            // [N][z]
+  std::vector<int32_t> eu, ev, ecls;   // canonical edges
+};
+
+namespace {
+
+// Greedy distance-2 edge colouring in canonical edge order: each edge takes the smallest
+// colour not held by an earlier edge incident to an endpoint or to a neighbour of an
+// endpoint.  Same-colour edges are then at distance >= 2, so they can be updated at once.
+int colour_edges(ka_graph &g)
+{
+  const int64_t E = (int64_t)g.eu.size();
+  std::vector<int64_t> inc((size_t)g.N * g.z, -1);
+  std::vector<int> fill((size_t)g.N, 0);
+  for (int64_t e = 0; e < E; ++e) {
+    inc[(size_t)g.eu[e] * g.z + fill[g.eu[e]]++] = e;
+    inc[(size_t)g.ev[e] * g.z + fill[g.ev[e]]++] = e;
+  }
+  g.ecls.assign((size_t)E, 0);
+  int ncol = 0;
+  std::vector<int32_t> verts;
+  for (int64_t e = 0; e < E; ++e) {
+    uint64_t used[4] = {0, 0, 0, 0};
+    verts.clear();
+    verts.push_back(g.eu[e]);
+    verts.push_back(g.ev[e]);
+    for (int k = 0; k < g.z; ++k) verts.push_back(g.adj[(size_t)g.eu[e] * g.z + k]);
+    for (int k = 0; k < g.z; ++k) verts.push_back(g.adj[(size_t)g.ev[e] * g.z + k]);
+    for (int32_t x : verts)
+      for (int k = 0; k < g.z; ++k) {
+        const int64_t f = inc[(size_t)x * g.z + k];
+        if (f >= 0 && f < e) used[g.ecls[f] >> 6] |= 1ull << (g.ecls[f] & 63);
+      }
+    int c = 0;
+    while (c < 256 && ((used[c >> 6] >> (c & 63)) & 1ull)) ++c;
+    if (c >= 256) return -1;
+    g.ecls[e] = c;
+    ncol = std::max(ncol, c + 1);
+  }
+  g.C = ncol;
+  return 0;
+}
+
+// Validate a z-regular simple adjacency, then build canonical edges and classes.
+int finish_general_graph(ka_graph &g)
+{
+  for (int64_t i = 0; i < g.N; ++i) {
+    const int32_t *row = &g.adj[(size_t)i * g.z];
+    for (int k = 0; k < g.z; ++k) {
+      const int64_t j = row[k];
+      if (j < 0 || j >= g.N) return fail(KA_EINVAL, "adjacency entry out of range at vertex %lld", (long long)i);
+      if (j == i) return fail(KA_EINVAL, "self-loop at vertex %lld", (long long)i);
+      for (int l = 0; l < k; ++l)
+        if (row[l] == j) return fail(KA_EINVAL, "repeated neighbour at vertex %lld", (long long)i);
+      const int32_t *back = &g.adj[(size_t)j * g.z];
+      if (std::find(back, back + g.z, (int32_t)i) == back + g.z)
+        return fail(KA_EINVAL, "adjacency not symmetric at edge (%lld, %lld)", (long long)i, (long long)j);
+    }
+  }
+  g.eu.clear();
+  g.ev.clear();
+  g.eu.reserve((size_t)(g.N * g.z / 2));
+  g.ev.reserve((size_t)(g.N * g.z / 2));
+  std::vector<int32_t> row((size_t)g.z);
+  for (int64_t u = 0; u < g.N; ++u) {
+    std::copy(&g.adj[(size_t)u * g.z], &g.adj[(size_t)u * g.z] + g.z, row.begin());
+    std::sort(row.begin(), row.end());
+    for (int32_t v : row)
+      if (v > u) {
+        g.eu.push_back((int32_t)u);
+        g.ev.push_back(v);
+      }
+  }
+  if (colour_edges(g) != 0) return fail(KA_EINVAL, "edge colouring needs more than 256 classes");
+  return KA_OK;
+}
+
+}  // namespace
+
+extern "C" int ka_graph_lattice(int d, int L, ka_graph **out)
+{
+  if (!out) return fail(KA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (d != 2 && d != 3) return fail(KA_EINVAL, "lattice dimension must be 2 or 3 (got %d)", d);
+  if (L < 4 || L % 4 != 0) return fail(KA_EINVAL, "lattice side must be a multiple of 4, >= 4 (got %d)", L);
+  int64_t N = 1;
+  for (int k = 0; k < d; ++k) N *= L;
+  if (N > (1ll << 30)) return fail(KA_EINVAL, "lattice too large (N = %lld > 2^30)", (long long)N);
+  ka_graph *g = new (std::nothrow) ka_graph;
+  if (!g) return fail(KA_ENOMEM, "host allocation failed");
+  g->lattice = 1;
+  g->d = d;
+  g->L = L;
+  g->N = N;
+  g->z = 2 * d;
+  g->C = 4 * d;
+  try {
+    g->adj.resize((size_t)N * g->z);
+    g->eu.resize((size_t)N * d);
+    g->ev.resize((size_t)N * d);
+    g->ecls.resize((size_t)N * d);
+  } catch (...) {
+    delete g;
+    return fail(KA_ENOMEM, "host allocation failed");
+  }
+  int64_t stride[3] = {1, L, (int64_t)L * L};
+  for (int64_t i = 0; i < N; ++i) {
+    int x[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) x[k] = (int)((i / stride[k]) % L);
+    int others_all = x[0] + x[1] + x[2];
+    for (int mu = 0; mu < d; ++mu) {
+      const int64_t up = i + (x[mu] + 1 < L ? stride[mu] : -(int64_t)(L - 1) * stride[mu]);
+      const int64_t dn = i + (x[mu] > 0 ? -stride[mu] : (int64_t)(L - 1) * stride[mu]);
+      g->adj[(size_t)i * g->z + 2 * mu] = (int32_t)up;
+      g->adj[(size_t)i * g->z + 2 * mu + 1] = (int32_t)dn;
+      const int64_t e = i * d + mu;
+      g->eu[e] = (int32_t)i;
+      g->ev[e] = (int32_t)up;
+      g->ecls[e] = 4 * mu + ((x[mu] + 2 * (others_all - x[mu])) & 3);
+    }
+  }
+  *out = g;
+  return KA_OK;
+}
+
+extern "C" int ka_graph_rrg(int64_t N, int z, uint64_t graph_seed, ka_graph **out)
+{
+  if (!out) return fail(KA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (z < 3 || z > 6) return fail(KA_EINVAL, "degree z must be in [3, 6] (got %d)", z);
+  if (N <= z || N > (1ll << 28) || (N * z) % 2 != 0)
+    return fail(KA_EINVAL, "need z < N <= 2^28 and N*z even (N = %lld, z = %d)", (long long)N, z);
+  ka_graph *g = new (std::nothrow) ka_graph;
+  if (!g) return fail(KA_ENOMEM, "host allocation failed");
+  g->N = N;
+  g->z = z;
+  const int64_t S = N * z;
+  std::vector<int32_t> stub, deg;
+  try {
+    stub.resize((size_t)S);
+    deg.resize((size_t)N);
+    g->adj.resize((size_t)S);
+  } catch (...) {
+    delete g;
+    return fail(KA_ENOMEM, "host allocation failed");
+  }
+  int32_t *adj = g->adj.data();
+  // Adds the edge (u, v) unless it is a self-loop or already present.
+  auto add_pair = [&](int32_t u, int32_t v) -> bool {
+    if (u == v) return false;
+    const int32_t *ru = adj + (size_t)u * z;
+    for (int k = 0; k < deg[u]; ++k)
+      if (ru[k] == v) return false;
+    adj[(size_t)u * z + deg[u]++] = v;
+    adj[(size_t)v * z + deg[v]++] = u;
+    return true;
+  };
+  bool found = false;
+  const int64_t max_attempts = 1000000;
+  for (int64_t a = 0; a < max_attempts && !found; ++a) {
+    WordStream ws(graph_seed, (uint32_t)a);
+    for (int64_t s = 0; s < S; ++s) stub[(size_t)s] = (int32_t)(s / z);
+    std::fill(deg.begin(), deg.end(), 0);
+    bool ok = true;
+    // Fisher-Yates from the top: after step k, positions k..S-1 are final, so the pair
+    // (2q, 2q+1) is known after step 2q and a bad pair ends the attempt early.  The
+    // attempt's random words do not depend on earlier attempts, so the accepted pairing
+    // is the same as with a complete shuffle followed by a check.
+    for (int64_t k = S - 1; k >= 1; --k) {
+      const int64_t j = ws.below((uint32_t)(k + 1));
+      std::swap(stub[(size_t)k], stub[(size_t)j]);
+      if ((k & 1) == 0 && !add_pair(stub[(size_t)k], stub[(size_t)k + 1])) {
+        ok = false;
+        break;
+      }
+    }
+    if (ok && !add_pair(stub[0], stub[1])) ok = false;
+    found = ok;
+  }
+  if (!found) {
+    delete g;
+    return fail(KA_ESTATE, "no simple pairing within %lld attempts", (long long)max_attempts);
+  }
+  for (int64_t i = 0; i < N; ++i) std::sort(adj + (size_t)i * z, adj + (size_t)i * z + z);
+  int rc = finish_general_graph(*g);
+  if (rc != KA_OK) {
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return KA_OK;
+}
+
+extern "C" int ka_graph_from_adjacency(int64_t N, int z, const int32_t *adj, ka_graph **out)
+{
+  if (!out || !adj) return fail(KA_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (z < 3 || z > 6) return fail(KA_EINVAL, "degree z must be in [3, 6] (got %d)", z);
+  if (N <= z || N > (1ll << 28)) return fail(KA_EINVAL, "need z < N <= 2^28 (N = %lld)", (long long)N);
+  ka_graph *g = new (std::nothrow) ka_graph;
+  if (!g) return fail(KA_ENOMEM, "host allocation failed");
+  g->N = N;
+  g->z = z;
+  try {
+    g->adj.assign(adj, adj + (size_t)N * z);
+  } catch (...) {
+    delete g;
+    return fail(KA_ENOMEM, "host allocation failed");
+  }
+  int rc = finish_general_graph(*g);
+  if (rc != KA_OK) {
+    delete g;
+    return rc;
+  }
+  *out = g;
+  return KA_OK;
+}
+
+extern "C" int ka_graph_info(const ka_graph *g, int64_t *N, int *z, int64_t *n_edges, int *n_classes)
+{
+  if (!g) return fail(KA_EINVAL, "graph is NULL");
+  if (N) *N = g->N;
+  if (z) *z = g->z;
+  if (n_edges) *n_edges = (int64_t)g->eu.size();
+  if (n_classes) *n_classes = g->C;
+  return KA_OK;
+}
+
+extern "C" int ka_graph_export(const ka_graph *g, int32_t *adj, int32_t *edge_u, int32_t *edge_v,
+                               int32_t *edge_class)
+{
+  if (!g) return fail(KA_EINVAL, "graph is NULL");
+  if (adj) std::memcpy(adj, g->adj.data(), g->adj.size() * sizeof(int32_t));
+  if (edge_u) std::memcpy(edge_u, g->eu.data(), g->eu.size() * sizeof(int32_t));
+  if (edge_v) std::memcpy(edge_v, g->ev.data(), g->ev.size() * sizeof(int32_t));
+  if (edge_class) std::memcpy(edge_class, g->ecls.data(), g->ecls.size() * sizeof(int32_t));
+  return KA_OK;
+}
+
+extern "C" void ka_graph_free(ka_graph *g) { delete g; }
+
+// ----------------------------------------------------------------------------------------
+// Simulation
+// ----------------------------------------------------------------------------------------
+struct ka_sim {
+  // graph summary
+  int lattice = 0;
+  int z = 0, C = 0;
+  int64_t N = 0;
+  ka::LatticeGeom geom{};
+  ka::LatticeClasses lcls{};
+  std::vector<int> class_start;   // general graphs: [C+1]
+  // parameters
+  int m = 0;
+  int64_t K = 0;
+  uint64_t seed = 0;
+  int R = 0, W = 0, wpt = 1, planes = 1;
+  int64_t t = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // device memory
+  u64 *n = nullptr, *n0 = nullptr, *f = nullptr;
+  int32_t *adj = nullptr;
+  int4 *edges = nullptr;
+  int *class_start_d = nullptr;
+  u64 *thr_u = nullptr;
+  long long *thr_i = nullptr;
+  int *err = nullptr;
+  unsigned long long *counts = nullptr;
+  size_t counts_cap = 0;
+  int64_t *obs_d = nullptr;
+  size_t obs_cap = 0;
+  // options and timing
+  bool init_checked = false;
+  int path_opt = 0;
+  size_t lds_bytes = 0;
+  bool lds_fits = false;
+  int64_t timing_every = 0;
+  int64_t launches = 0;
+  int64_t timed = 0;
+  double timed_ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<hipEvent_t> event_pool;
+};
+
+namespace {
+
+size_t state_bytes(int64_t N, int R) { return (size_t)3 * (size_t)N * (size_t)(R / 64) * 8u; }
+
+size_t graph_device_bytes(const ka_graph *g)
+{
+  if (g->lattice) return 0;
+  return g->adj.size() * 4u + g->eu.size() * sizeof(int4) + (size_t)(g->C + 1) * sizeof(int);
+}
+
+void free_device(ka_sim *s)
+{
+  (void)hipFree(s->n);
+  (void)hipFree(s->n0);
+  (void)hipFree(s->f);
+  (void)hipFree(s->adj);
+  (void)hipFree(s->edges);
+  (void)hipFree(s->class_start_d);
+  (void)hipFree(s->thr_u);
+  (void)hipFree(s->thr_i);
+  (void)hipFree(s->err);
+  (void)hipFree(s->counts);
+  (void)hipFree(s->obs_d);
+  s->n = s->n0 = s->f = nullptr;
+}
+
+template <typename T>
+hipError_t dalloc(T **p, size_t bytes)
+{
+  return hipMalloc(reinterpret_cast<void **>(p), bytes ? bytes : 16);
+}
+
+// Lower-endpoint sublattices of lattice class c = 4*mu + r: residue vectors a with
+// (a_mu + 2 * sum_{nu != mu} a_nu) mod 4 == r, in increasing sub code.
+void lattice_class_tables(int d, ka::LatticeClasses &t)
+{
+  t.nsub = d == 2 ? 4 : 16;
+  const int nsubs = d == 2 ? 16 : 64;
+  for (int c = 0; c < 4 * d; ++c) {
+    const int mu = c >> 2, r = c & 3;
+    int k = 0;
+    for (int sub = 0; sub < nsubs; ++sub) {
+      const int a[3] = {sub & 3, (sub >> 2) & 3, (sub >> 4) & 3};
+      const int others = a[0] + a[1] + a[2] - a[mu];
+      if (((a[mu] + 2 * others) & 3) == r) t.sub[c][k++] = sub;
+    }
+  }
+}
+
+// Element index of canonical site i in the lattice device layout.
+inline int64_t lattice_element(const ka::LatticeGeom &g, int64_t i)
+{
+  int64_t sub = 0, pos = 0, sm = 1, pm = 1;
+  for (int k = 0; k < g.d; ++k) {
+    const int x = (int)(i % g.L);
+    i /= g.L;
+    sub += (x & 3) * sm;
+    pos += (x >> 2) * pm;
+    sm *= 4;
+    pm *= g.Q;
+  }
+  return sub * g.P + pos;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev)
+  {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~DeviceGuard()
+  {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+bool use_lds(const ka_sim *s)
+{
+  if (s->path_opt == 1) return false;
+  if (s->path_opt == 2) return s->lds_fits;
+  return s->lds_fits;
+}
+
+hipEvent_t pooled_event(ka_sim *s)
+{
+  if (!s->event_pool.empty()) {
+    hipEvent_t e = s->event_pool.back();
+    s->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Collect the durations of completed timed launches (call after a stream sync).
+void harvest_timing(ka_sim *s)
+{
+  for (auto &pr : s->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      s->timed_ms += ms;
+      s->timed += 1;
+    }
+    s->event_pool.push_back(pr.first);
+    s->event_pool.push_back(pr.second);
+  }
+  s->pending.clear();
+}
+
+// One class pass over global memory.
+hipError_t launch_class(ka_sim *s, int c, uint32_t t)
+{
+  const uint32_t k0 = (uint32_t)s->seed, k1 = (uint32_t)(s->seed >> 32);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  const bool timed = s->timing_every > 0 && (s->launches % s->timing_every) == 0;
+  if (timed) {
+    e0 = pooled_event(s);
+    e1 = pooled_event(s);
+    (void)hipEventRecord(e0, s->stream);
+  }
+  hipError_t err;
+  if (s->lattice) {
+    ka::PassLattice a{};
+    a.n = s->n;
+    a.f = s->f;
+    a.g = s->geom;
+    a.mu = c >> 2;
+    a.nsub = s->lcls.nsub;
+    for (int q = 0; q < a.nsub; ++q) a.sub[q] = s->lcls.sub[c][q];
+    a.planes = s->planes;
+    const int per_plane = a.nsub * s->geom.P;
+    a.blocks_per_plane = (per_plane + 255) / 256;
+    a.t = t;
+    a.c = (uint32_t)c;
+    a.key0 = k0;
+    a.key1 = k1;
+    err = ka::launch_pass_lattice(a, s->m, s->wpt, s->stream);
+  } else {
+    ka::PassGraph a{};
+    a.n = s->n;
+    a.f = s->f;
+    a.adj = s->adj;
+    a.edges = s->edges + s->class_start[c];
+    a.count = s->class_start[c + 1] - s->class_start[c];
+    a.N = (int)s->N;
+    a.planes = s->planes;
+    a.blocks_per_plane = (a.count + 255) / 256;
+    a.t = t;
+    a.c = (uint32_t)c;
+    a.key0 = k0;
+    a.key1 = k1;
+    err = a.count > 0 ? ka::launch_pass_graph(a, s->z, s->m, s->wpt, s->stream) : hipSuccess;
+  }
+  if (timed) {
+    (void)hipEventRecord(e1, s->stream);
+    s->pending.emplace_back(e0, e1);
+  }
+  s->launches += 1;
+  return err;
+}
+
+constexpr int64_t kLdsChunk = 20000;  // sweeps per LDS-resident launch
+
+hipError_t ensure_obs_buffers(ka_sim *s, size_t n_obs)
+{
+  const size_t need = n_obs * 3u * (size_t)s->R;
+  if (need > s->counts_cap) {
+    (void)hipFree(s->counts);
+    s->counts = nullptr;
+    s->counts_cap = 0;
+    hipError_t e = dalloc(&s->counts, need * sizeof(unsigned long long));
+    if (e != hipSuccess) return e;
+    s->counts_cap = need;
+  }
+  if (n_obs > s->obs_cap) {
+    (void)hipFree(s->obs_d);
+    s->obs_d = nullptr;
+    s->obs_cap = 0;
+    hipError_t e = dalloc(&s->obs_d, n_obs * sizeof(int64_t));
+    if (e != hipSuccess) return e;
+    s->obs_cap = n_obs;
+  }
+  return hipSuccess;
+}
+
+// LDS-resident launch covering sweeps [t_from, t_to) that also records observations
+// obs[q0..q1) (absolute times) into counts rows q0..q1.
+hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
+{
+  ka::SweepLds a{};
+  a.n = s->n;
+  a.f = s->f;
+  a.n0 = s->n0;
+  a.g = s->geom;
+  a.cls = s->lcls;
+  a.adj = s->adj;
+  a.edges = s->edges;
+  a.class_start = s->class_start_d;
+  a.N = (int)s->N;
+  a.C = s->C;
+  a.t0 = (uint32_t)t_from;
+  a.n_sweeps = (int)(t_to - t_from);
+  a.obs_times = s->obs_d + q0;
+  a.n_obs = q1 - q0;
+  a.obs_out = s->counts + (size_t)q0 * 3u * (size_t)s->R;
+  a.R = s->R;
+  a.key0 = (uint32_t)s->seed;
+  a.key1 = (uint32_t)(s->seed >> 32);
+  return ka::launch_sweep_lds(a, s->lattice != 0, s->z, s->m, s->wpt, s->lds_bytes, s->stream);
+}
+
+hipError_t sweep_global(ka_sim *s, int64_t n)
+{
+  for (int64_t q = 0; q < n; ++q) {
+    const uint32_t t = (uint32_t)(s->t + q);
+    for (int c = 0; c < s->C; ++c) {
+      hipError_t e = launch_class(s, c, t);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+hipError_t observe_global(ka_sim *s, int row)
+{
+  ka::ObserveArgs a{};
+  a.n = s->n;
+  a.n0 = s->n0;
+  a.f = s->f;
+  a.N = (int)s->N;
+  a.planes = s->planes;
+  a.R = s->R;
+  a.out = s->counts + (size_t)row * 3u * (size_t)s->R;
+  return ka::launch_observe(a, s->wpt, s->stream);
+}
+
+// After a stream synchronisation: report a failure flagged by the initial-state kernels.
+int check_init_flag(ka_sim *s)
+{
+  if (s->init_checked) return KA_OK;
+  int flag = 0;
+  hipError_t e = hipMemcpy(&flag, s->err, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "reading the init status");
+  s->init_checked = true;
+  if (flag) return fail(KA_EDEVICE, "initial-state selection failed (flag %d)", flag);
+  return KA_OK;
+}
+
+int check_sim(const ka_sim *s)
+{
+  if (!s) return fail(KA_EINVAL, "sim is NULL");
+  if (!s->n) return fail(KA_ESTATE, "sim has no device state");
+  return KA_OK;
+}
+
+}  // namespace
+
+extern "C" int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_bytes)
+{
+  if (!g || !device_bytes) return fail(KA_EINVAL, "NULL argument");
+  if (n_replicas <= 0 || n_replicas % 64 != 0) return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
+  *device_bytes = state_bytes(g->N, n_replicas) + graph_device_bytes(g) +
+                  (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u;
+  return KA_OK;
+}
+
+extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int n_replicas,
+                         void *hip_stream, ka_sim **out)
+{
+  if (!out) return fail(KA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!g) return fail(KA_EINVAL, "graph is NULL");
+  if (m < 0 || m > g->z - 1) return fail(KA_EINVAL, "activation number m must be in [0, z-1] = [0, %d] (got %d)", g->z - 1, m);
+  if (n_replicas <= 0 || n_replicas % 64 != 0)
+    return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64 (got %d)", n_replicas);
+  if (K < 0 || K > g->N) return fail(KA_EINVAL, "particle number K must be in [0, N] (got %lld)", (long long)K);
+  ka_sim *s = new (std::nothrow) ka_sim;
+  if (!s) return fail(KA_ENOMEM, "host allocation failed");
+  s->lattice = g->lattice;
+  s->z = g->z;
+  s->C = g->C;
+  s->N = g->N;
+  s->m = m;
+  s->K = K;
+  s->seed = seed;
+  s->R = n_replicas;
+  s->W = n_replicas / 64;
+  s->wpt = (s->W % 2 == 0) ? 2 : 1;
+  s->planes = s->W / s->wpt;
+  (void)hipGetDevice(&s->device);
+  if (hip_stream) {
+    s->stream = (hipStream_t)hip_stream;
+  } else {
+    hipError_t e = hipStreamCreate(&s->stream);
+    if (e != hipSuccess) {
+      delete s;
+      return hip_fail(e, "hipStreamCreate");
+    }
+    s->own_stream = true;
+  }
+  const size_t words = (size_t)s->N * s->W;
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = dalloc(&s->n, words * 8);
+  if (e == hipSuccess) e = dalloc(&s->n0, words * 8);
+  if (e == hipSuccess) e = dalloc(&s->f, words * 8);
+  if (e == hipSuccess) e = dalloc(&s->thr_u, (size_t)s->R * 8);
+  if (e == hipSuccess) e = dalloc(&s->thr_i, (size_t)s->R * 8);
+  if (e == hipSuccess) e = dalloc(&s->err, sizeof(int));
+  if (e != hipSuccess) {
+    free_device(s);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return fail(KA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+  }
+  if (s->lattice) {
+    s->geom.d = g->d;
+    s->geom.L = g->L;
+    s->geom.Q = g->L / 4;
+    s->geom.P = g->d == 2 ? s->geom.Q * s->geom.Q : s->geom.Q * s->geom.Q * s->geom.Q;
+    s->geom.N = (int)g->N;
+    lattice_class_tables(g->d, s->lcls);
+  } else {
+    // class-sorted edge records (u, v, e, 0), edges of one class in increasing e
+    const int64_t E = (int64_t)g->eu.size();
+    s->class_start.assign((size_t)g->C + 1, 0);
+    for (int64_t q = 0; q < E; ++q) s->class_start[(size_t)g->ecls[q] + 1]++;
+    for (int c = 0; c < g->C; ++c) s->class_start[(size_t)c + 1] += s->class_start[(size_t)c];
+    std::vector<int> fill(s->class_start.begin(), s->class_start.end() - 1);
+    std::vector<int4> rec((size_t)E);
+    for (int64_t q = 0; q < E; ++q) rec[(size_t)fill[(size_t)g->ecls[q]]++] = make_int4(g->eu[q], g->ev[q], (int)q, 0);
+    e = dalloc(&s->adj, g->adj.size() * 4);
+    if (e == hipSuccess) e = dalloc(&s->edges, rec.size() * sizeof(int4));
+    if (e == hipSuccess) e = dalloc(&s->class_start_d, s->class_start.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpy(s->adj, g->adj.data(), g->adj.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(s->class_start_d, s->class_start.data(), s->class_start.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      free_device(s);
+      if (s->own_stream) (void)hipStreamDestroy(s->stream);
+      delete s;
+      return fail(KA_ENOMEM, "device allocation/copy failed: %s", hipGetErrorString(e));
+    }
+  }
+  s->lds_bytes = ka::sweep_lds_bytes((int)s->N, s->wpt);
+  s->lds_fits = s->lds_bytes + 4096 <= (size_t)ka::max_lds_bytes();
+  // initial state
+  ka::InitArgs a{};
+  a.N = (int)s->N;
+  a.K = K;
+  a.key0 = (uint32_t)seed;
+  a.key1 = (uint32_t)(seed >> 32);
+  a.thr_u = s->thr_u;
+  a.thr_i = s->thr_i;
+  a.err = s->err;
+  a.n = s->n;
+  a.n0 = s->n0;
+  a.f = s->f;
+  a.planes = s->planes;
+  a.is_lattice = s->lattice;
+  a.g = s->geom;
+  e = hipMemsetAsync(s->err, 0, sizeof(int), s->stream);
+  if (e == hipSuccess) e = ka::launch_init(a, s->R, s->wpt, s->stream);
+  if (e != hipSuccess) {
+    free_device(s);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return hip_fail(e, "init kernels");
+  }
+  *out = s;
+  return KA_OK;
+}
+
+extern "C" int ka_init(const ka_graph *g, int m, double rho, uint64_t seed, int n_replicas,
+                       void *hip_stream, ka_sim **out)
+{
+  if (!g) return fail(KA_EINVAL, "graph is NULL");
+  if (!(rho >= 0.0 && rho <= 1.0)) return fail(KA_EINVAL, "density rho must be in [0, 1]");
+  const int64_t K = (int64_t)std::floor(rho * (double)g->N + 0.5);
+  return ka_init_k(g, m, K, seed, n_replicas, hip_stream, out);
+}
+
+extern "C" int ka_sweep(ka_sim *s, int64_t n_sweeps)
+{
+  int rc = check_sim(s);
+  if (rc) return rc;
+  if (n_sweeps < 0) return fail(KA_EINVAL, "n_sweeps < 0");
+  if (s->t + n_sweeps >= (1ll << 32)) return fail(KA_ESTATE, "sweep index would reach 2^32");
+  DeviceGuard dg(s->device);
+  hipError_t e = hipSuccess;
+  if (use_lds(s)) {
+    int64_t done = 0;
+    while (done < n_sweeps && e == hipSuccess) {
+      const int64_t chunk = std::min(kLdsChunk, n_sweeps - done);
+      e = ensure_obs_buffers(s, 1);
+      if (e == hipSuccess) e = launch_lds(s, s->t + done, s->t + done + chunk, 0, 0);
+      done += chunk;
+    }
+  } else {
+    e = sweep_global(s, n_sweeps);
+  }
+  if (e != hipSuccess) return hip_fail(e, "ka_sweep");
+  s->t += n_sweeps;
+  return KA_OK;
+}
+
+extern "C" int ka_run(ka_sim *s, const int64_t *obs_times, int n_obs, int64_t *density,
+                      int64_t *overlap, int64_t *persistence)
+{
+  int rc = check_sim(s);
+  if (rc) return rc;
+  if (n_obs < 0 || (n_obs > 0 && !obs_times)) return fail(KA_EINVAL, "bad observation list");
+  int64_t prev = s->t;
+  for (int q = 0; q < n_obs; ++q) {
+    if (obs_times[q] < prev) return fail(KA_EINVAL, "observation times must be non-decreasing and >= t");
+    prev = obs_times[q];
+  }
+  if (prev >= (1ll << 32)) return fail(KA_ESTATE, "sweep index would reach 2^32");
+  if (n_obs == 0) return KA_OK;
+  DeviceGuard dg(s->device);
+  hipError_t e = ensure_obs_buffers(s, (size_t)n_obs);
+  if (e != hipSuccess) return fail(KA_ENOMEM, "observation buffers: %s", hipGetErrorString(e));
+  const size_t cbytes = (size_t)n_obs * 3u * (size_t)s->R * sizeof(unsigned long long);
+  e = hipMemsetAsync(s->counts, 0, cbytes, s->stream);
+  if (e == hipSuccess && use_lds(s)) {
+    e = hipMemcpyAsync(s->obs_d, obs_times, (size_t)n_obs * sizeof(int64_t), hipMemcpyHostToDevice, s->stream);
+    // chunks [a, b) of at most kLdsChunk sweeps; observation q goes to the first chunk
+    // that can record it (times in [a, b] for the first chunk, (a, b] afterwards)
+    int q = 0;
+    int64_t a = s->t;
+    bool first = true;
+    while (e == hipSuccess && q < n_obs) {
+      const int64_t b = std::min(a + kLdsChunk, obs_times[n_obs - 1]);
+      int q1 = q;
+      while (q1 < n_obs && obs_times[q1] <= b && (first || obs_times[q1] > a)) ++q1;
+      e = launch_lds(s, a, b, q, q1);
+      q = q1;
+      a = b;
+      first = false;
+    }
+  } else {
+    for (int q = 0; q < n_obs && e == hipSuccess; ++q) {
+      const int64_t n = obs_times[q] - s->t;
+      e = sweep_global(s, n);
+      s->t = obs_times[q];
+      if (e == hipSuccess) e = observe_global(s, q);
+    }
+  }
+  s->t = obs_times[n_obs - 1];
+  std::vector<unsigned long long> host((size_t)n_obs * 3u * (size_t)s->R);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), s->counts, cbytes, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(e, "ka_run");
+  rc = check_init_flag(s);
+  if (rc) return rc;
+  harvest_timing(s);
+  for (int q = 0; q < n_obs; ++q)
+    for (int b = 0; b < s->R; ++b) {
+      const size_t base = (size_t)q * 3u * s->R;
+      if (density) density[(size_t)q * s->R + b] = (int64_t)host[base + b];
+      if (overlap) overlap[(size_t)q * s->R + b] = (int64_t)host[base + s->R + b];
+      if (persistence) persistence[(size_t)q * s->R + b] = (int64_t)host[base + 2u * s->R + b];
+    }
+  return KA_OK;
+}
+
+extern "C" int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
+                          int64_t *persistence)
+{
+  int rc = check_sim(s);
+  if (rc) return rc;
+  const int64_t now = s->t;
+  rc = ka_run(s, &now, 1, density, overlap, persistence);
+  if (rc) return rc;
+  if (t) *t = s->t;
+  return KA_OK;
+}
+
+extern "C" int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, int64_t *t)
+{
+  int rc = check_sim(s);
+  if (rc) return rc;
+  DeviceGuard dg(s->device);
+  const size_t words = (size_t)s->N * s->W;
+  std::vector<u64> buf(words);
+  uint64_t *outs[3] = {n, n0, f};
+  u64 *srcs[3] = {s->n, s->n0, s->f};
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(e, "ka_get_state");
+  rc = check_init_flag(s);
+  if (rc) return rc;
+  for (int k = 0; k < 3; ++k) {
+    if (!outs[k]) continue;
+    e = hipMemcpy(buf.data(), srcs[k], words * 8, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "ka_get_state copy");
+    for (int64_t i = 0; i < s->N; ++i) {
+      const int64_t el = s->lattice ? lattice_element(s->geom, i) : i;
+      for (int p = 0; p < s->planes; ++p)
+        for (int w = 0; w < s->wpt; ++w)
+          outs[k][(size_t)(p * s->wpt + w) * s->N + i] = buf[((size_t)p * s->N + el) * s->wpt + w];
+    }
+  }
+  if (t) *t = s->t;
+  return KA_OK;
+}
+
+extern "C" int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, const uint64_t *f,
+                            int64_t t)
+{
+  int rc = check_sim(s);
+  if (rc) return rc;
+  if (!n || !n0 || !f) return fail(KA_EINVAL, "ka_set_state needs n, n0 and f");
+  if (t < 0 || t >= (1ll << 32)) return fail(KA_EINVAL, "t out of range");
+  DeviceGuard dg(s->device);
+  const size_t words = (size_t)s->N * s->W;
+  std::vector<u64> buf(words);
+  const uint64_t *ins[3] = {n, n0, f};
+  u64 *dsts[3] = {s->n, s->n0, s->f};
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(e, "ka_set_state");
+  for (int k = 0; k < 3; ++k) {
+    for (int64_t i = 0; i < s->N; ++i) {
+      const int64_t el = s->lattice ? lattice_element(s->geom, i) : i;
+      for (int p = 0; p < s->planes; ++p)
+        for (int w = 0; w < s->wpt; ++w)
+          buf[((size_t)p * s->N + el) * s->wpt + w] = ins[k][(size_t)(p * s->wpt + w) * s->N + i];
+    }
+    e = hipMemcpy(dsts[k], buf.data(), words * 8, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "ka_set_state copy");
+  }
+  s->t = t;
+  return KA_OK;
+}
+
+extern "C" int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t *K, int *m,
+                           int64_t *t, int *n_classes)
+{
+  if (!s) return fail(KA_EINVAL, "sim is NULL");
+  if (N) *N = s->N;
+  if (n_replicas) *n_replicas = s->R;
+  if (K) *K = s->K;
+  if (m) *m = s->m;
+  if (t) *t = s->t;
+  if (n_classes) *n_classes = s->C;
+  return KA_OK;
+}
+
+extern "C" int ka_set_option(ka_sim *s, int option, int64_t value)
+{
+  if (!s) return fail(KA_EINVAL, "sim is NULL");
+  if (option == KA_OPT_PATH) {
+    if (value < 0 || value > 2) return fail(KA_EINVAL, "path must be 0, 1 or 2");
+    if (value == 2 && !s->lds_fits) return fail(KA_EINVAL, "instance does not fit in LDS");
+    s->path_opt = (int)value;
+    return KA_OK;
+  }
+  if (option == KA_OPT_TIMING) {
+    if (value < 0) return fail(KA_EINVAL, "timing interval must be >= 0");
+    s->timing_every = value;
+    return KA_OK;
+  }
+  return fail(KA_EINVAL, "unknown option %d", option);
+}
+
+extern "C" int ka_timing(ka_sim *s, int64_t *launches, int64_t *timed, double *timed_ms)
+{
+  if (!s) return fail(KA_EINVAL, "sim is NULL");
+  DeviceGuard dg(s->device);
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return hip_fail(e, "ka_timing");
+  harvest_timing(s);
+  if (launches) *launches = s->launches;
+  if (timed) *timed = s->timed;
+  if (timed_ms) *timed_ms = s->timed_ms;
+  return KA_OK;
+}
+
+extern "C" int ka_sim_path(const ka_sim *s, int *path)
+{
+  if (!s || !path) return fail(KA_EINVAL, "NULL argument");
+  *path = use_lds(s) ? 2 : 1;
+  return KA_OK;
+}
+
+extern "C" void ka_free(ka_sim *s)
+{
+  if (!s) return;
+  DeviceGuard dg(s->device);
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  harvest_timing(s);
+  for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
+  free_device(s);
+  if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  delete s;
+}
+
+extern "C" const char *ka_last_error(void) { return g_err.c_str(); }

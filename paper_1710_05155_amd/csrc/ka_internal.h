@@ -1,0 +1,119 @@
+// ka_internal.h -- launch descriptors shared by the libka host code and its HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ka {
+
+typedef unsigned long long u64;
+
+// Device layout of a word plane of a lattice sim: sites are grouped by their coordinate
+// residues a_nu = x_nu mod 4 ("sublattice" sub = sum_nu a_nu 4^nu); inside a sublattice by
+// their block coordinates p_nu = x_nu / 4 (pos = sum_nu p_nu Q^nu, Q = L/4).  Element index
+// = sub * P + pos with P = Q^d.  Every edge class is a union of whole sublattices (its lower
+// endpoints), so one pass writes exactly half of the sublattices and threads that walk pos
+// read and write consecutive addresses.  General graphs use the vertex id as index.
+// An element holds wpt consecutive 64-bit words (wpt = 2 when the replica count is a
+// multiple of 128: word pair p = words 2p, 2p+1; else 1); plane p covers words
+// p*wpt .. p*wpt+wpt-1.
+
+struct LatticeGeom {
+  int d;        // 2 or 3
+  int L;        // side
+  int Q;        // L / 4
+  int P;        // Q^d, elements per sublattice
+  int N;        // L^d
+};
+
+// Lower-endpoint sublattices of each class (4^(d-1) of them, increasing sub code).
+struct LatticeClasses {
+  int nsub;               // 4^(d-1)
+  int sub[12][16];        // [class][k]
+};
+
+struct PassLattice {
+  u64 *n;
+  u64 *f;
+  LatticeGeom g;
+  int mu;
+  int nsub;
+  int sub[16];
+  int planes;
+  int blocks_per_plane;
+  uint32_t t, c, key0, key1;
+};
+
+struct PassGraph {
+  u64 *n;
+  u64 *f;
+  const int32_t *adj;        // [N][z]
+  const int4 *edges;         // class slice: (u, v, e, 0)
+  int count;                 // edges in the class
+  int N;
+  int planes;
+  int blocks_per_plane;
+  uint32_t t, c, key0, key1;
+};
+
+// Whole sweep loop inside one workgroup per plane (plane in LDS).
+struct SweepLds {
+  u64 *n;
+  u64 *f;
+  const u64 *n0;
+  // lattice
+  LatticeGeom g;
+  LatticeClasses cls;
+  // graph
+  const int32_t *adj;
+  const int4 *edges;         // all edges sorted by (class, e)
+  const int *class_start;    // [C+1]
+  int N;
+  int C;
+  uint32_t t0;
+  int n_sweeps;
+  // observations: absolute sweep indices (non-decreasing), rows of out [n_obs][3][R]
+  const int64_t *obs_times;
+  int n_obs;
+  unsigned long long *obs_out;
+  int R;
+  uint32_t key0, key1;
+};
+
+struct InitArgs {
+  int N;
+  int64_t K;
+  uint32_t key0, key1;
+  u64 *thr_u;         // [R]
+  long long *thr_i;   // [R]
+  int *err;
+  // fill
+  u64 *n;
+  u64 *n0;
+  u64 *f;
+  int planes;
+  int is_lattice;
+  LatticeGeom g;
+};
+
+struct ObserveArgs {
+  const u64 *n;
+  const u64 *n0;
+  const u64 *f;
+  int N;
+  int planes;
+  int R;
+  unsigned long long *out;   // [3][R]: density, overlap, persistence
+};
+
+// Launchers (ka_kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_pass_lattice(const PassLattice &a, int m, int wpt, hipStream_t s);
+hipError_t launch_pass_graph(const PassGraph &a, int z, int m, int wpt, hipStream_t s);
+hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, int wpt,
+                            size_t lds_bytes, hipStream_t s);
+hipError_t launch_init(const InitArgs &a, int R, int wpt, hipStream_t s);
+hipError_t launch_observe(const ObserveArgs &a, int wpt, hipStream_t s);
+size_t sweep_lds_bytes(int N, int wpt);
+int max_lds_bytes();
+
+}  // namespace ka

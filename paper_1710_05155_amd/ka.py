@@ -1,0 +1,324 @@
+"""Thin ctypes binding of libka (include/ka.h).  Argument marshalling only: every step of
+the sweep runs in the library's HIP kernels; torch is used, if at all, only to hand over a
+HIP stream.  Importing this module does not touch the GPU; loading the library does not
+either.  There is no fallback: if libka.so is missing, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libka.so")
+
+KA_OK = 0
+KA_EINVAL = -1
+KA_ENOMEM = -2
+KA_EDEVICE = -3
+KA_ESTATE = -4
+KA_OPT_PATH = 1
+KA_OPT_TIMING = 2
+
+# Every symbol include/ka.h declares.
+SYMBOLS = (
+    "ka_graph_lattice", "ka_graph_rrg", "ka_graph_from_adjacency", "ka_graph_info",
+    "ka_graph_export", "ka_graph_free", "ka_footprint", "ka_init", "ka_init_k", "ka_sweep",
+    "ka_observe", "ka_run", "ka_get_state", "ka_set_state", "ka_sim_info", "ka_set_option",
+    "ka_timing", "ka_sim_path", "ka_free", "ka_last_error",
+)
+
+
+class KaError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libka error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load():
+    """Load libka.so (built in-tree by build.py); raises if it is absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise KaError(KA_EDEVICE, f"{LIB_PATH} is not built (run paper_1710_05155_amd/build.py)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    I = ctypes.c_int
+    I64 = ctypes.c_int64
+    U64 = ctypes.c_uint64
+    D = ctypes.c_double
+    sig = {
+        "ka_graph_lattice": ([I, I, PP], I),
+        "ka_graph_rrg": ([I64, I, U64, PP], I),
+        "ka_graph_from_adjacency": ([I64, I, P, PP], I),
+        "ka_graph_info": ([P, P, P, P, P], I),
+        "ka_graph_export": ([P, P, P, P, P], I),
+        "ka_graph_free": ([P], None),
+        "ka_footprint": ([P, I, P], I),
+        "ka_init": ([P, I, D, U64, I, P, PP], I),
+        "ka_init_k": ([P, I, I64, U64, I, P, PP], I),
+        "ka_sweep": ([P, I64], I),
+        "ka_observe": ([P, P, P, P, P], I),
+        "ka_run": ([P, P, I, P, P, P], I),
+        "ka_get_state": ([P, P, P, P, P], I),
+        "ka_set_state": ([P, P, P, P, I64], I),
+        "ka_sim_info": ([P, P, P, P, P, P, P], I),
+        "ka_set_option": ([P, I, I64], I),
+        "ka_timing": ([P, P, P, P], I),
+        "ka_sim_path": ([P, P], I),
+        "ka_free": ([P], None),
+        "ka_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != KA_OK:
+        msg = load().ka_last_error()
+        raise KaError(rc, msg.decode() if msg else "")
+
+
+def _ptr(a: np.ndarray | None):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)  # torch.cuda.Stream
+
+
+class Graph:
+    """Owning handle of a ka_graph."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+        N = ctypes.c_int64()
+        z = ctypes.c_int()
+        E = ctypes.c_int64()
+        C = ctypes.c_int()
+        _check(load().ka_graph_info(self._h, ctypes.byref(N), ctypes.byref(z), ctypes.byref(E),
+                                    ctypes.byref(C)))
+        self.N, self.z, self.E, self.C = N.value, z.value, E.value, C.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ka_graph_free(self._h)
+            self._h = None
+
+
+class Sim:
+    """Owning handle of a ka_sim."""
+
+    def __init__(self, handle: ctypes.c_void_p, graph: Graph, stream):
+        self._h = handle
+        self.graph = graph
+        self.stream = stream
+        N = ctypes.c_int64()
+        R = ctypes.c_int()
+        K = ctypes.c_int64()
+        m = ctypes.c_int()
+        t = ctypes.c_int64()
+        C = ctypes.c_int()
+        _check(load().ka_sim_info(self._h, ctypes.byref(N), ctypes.byref(R), ctypes.byref(K),
+                                  ctypes.byref(m), ctypes.byref(t), ctypes.byref(C)))
+        self.N, self.R, self.K, self.m, self.C = N.value, R.value, K.value, m.value, C.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def t(self) -> int:
+        t = ctypes.c_int64()
+        _check(load().ka_sim_info(self._h, None, None, None, None, ctypes.byref(t), None))
+        return t.value
+
+    def free(self):
+        if self._h and _lib is not None:
+            _lib.ka_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+# ------------------------------------------------------------------------------ graphs
+def ka_graph_lattice(d: int, L: int) -> Graph:
+    h = ctypes.c_void_p()
+    _check(load().ka_graph_lattice(d, L, ctypes.byref(h)))
+    return Graph(h)
+
+
+def ka_graph_rrg(N: int, z: int, graph_seed: int) -> Graph:
+    h = ctypes.c_void_p()
+    _check(load().ka_graph_rrg(N, z, graph_seed, ctypes.byref(h)))
+    return Graph(h)
+
+
+def ka_graph_from_adjacency(adj) -> Graph:
+    adj = np.ascontiguousarray(adj, dtype=np.int32)
+    N, z = adj.shape
+    h = ctypes.c_void_p()
+    _check(load().ka_graph_from_adjacency(N, z, _ptr(adj), ctypes.byref(h)))
+    return Graph(h)
+
+
+def ka_graph_info(g: Graph):
+    return g.N, g.z, g.E, g.C
+
+
+def ka_graph_export(g: Graph):
+    adj = np.empty((g.N, g.z), dtype=np.int32)
+    eu = np.empty(g.E, dtype=np.int32)
+    ev = np.empty(g.E, dtype=np.int32)
+    ec = np.empty(g.E, dtype=np.int32)
+    _check(load().ka_graph_export(g.handle, _ptr(adj), _ptr(eu), _ptr(ev), _ptr(ec)))
+    return adj, eu, ev, ec
+
+
+def ka_footprint(g: Graph, n_replicas: int) -> int:
+    out = ctypes.c_size_t()
+    _check(load().ka_footprint(g.handle, n_replicas, ctypes.byref(out)))
+    return int(out.value)
+
+
+# ------------------------------------------------------------------------------ sims
+def ka_init(g: Graph, m: int, rho: float, seed: int, n_replicas: int, stream=None) -> Sim:
+    h = ctypes.c_void_p()
+    _check(load().ka_init(g.handle, m, float(rho), seed, n_replicas, _stream_handle(stream),
+                          ctypes.byref(h)))
+    return Sim(h, g, stream)
+
+
+def ka_init_k(g: Graph, m: int, K: int, seed: int, n_replicas: int, stream=None) -> Sim:
+    h = ctypes.c_void_p()
+    _check(load().ka_init_k(g.handle, m, int(K), seed, n_replicas, _stream_handle(stream),
+                            ctypes.byref(h)))
+    return Sim(h, g, stream)
+
+
+def ka_sweep(s: Sim, n_sweeps: int) -> None:
+    _check(load().ka_sweep(s.handle, int(n_sweeps)))
+
+
+def ka_observe(s: Sim):
+    t = ctypes.c_int64()
+    dens = np.empty(s.R, dtype=np.int64)
+    ov = np.empty(s.R, dtype=np.int64)
+    pers = np.empty(s.R, dtype=np.int64)
+    _check(load().ka_observe(s.handle, ctypes.byref(t), _ptr(dens), _ptr(ov), _ptr(pers)))
+    return t.value, dens, ov, pers
+
+
+def ka_run(s: Sim, obs_times):
+    times = np.ascontiguousarray(np.asarray(obs_times, dtype=np.int64))
+    n = times.shape[0]
+    dens = np.empty((n, s.R), dtype=np.int64)
+    ov = np.empty((n, s.R), dtype=np.int64)
+    pers = np.empty((n, s.R), dtype=np.int64)
+    _check(load().ka_run(s.handle, _ptr(times), n, _ptr(dens), _ptr(ov), _ptr(pers)))
+    return dens, ov, pers
+
+
+def ka_get_state(s: Sim):
+    W = s.R // 64
+    n = np.empty((W, s.N), dtype=np.uint64)
+    n0 = np.empty((W, s.N), dtype=np.uint64)
+    f = np.empty((W, s.N), dtype=np.uint64)
+    t = ctypes.c_int64()
+    _check(load().ka_get_state(s.handle, _ptr(n), _ptr(n0), _ptr(f), ctypes.byref(t)))
+    return n, n0, f, t.value
+
+
+def ka_set_state(s: Sim, n, n0, f, t: int) -> None:
+    W = s.R // 64
+    arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.uint64).reshape(W, s.N)) for a in (n, n0, f)]
+    _check(load().ka_set_state(s.handle, _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]), int(t)))
+
+
+def ka_set_option(s: Sim, option: int, value: int) -> None:
+    _check(load().ka_set_option(s.handle, option, int(value)))
+
+
+def ka_timing(s: Sim):
+    launches = ctypes.c_int64()
+    timed = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load().ka_timing(s.handle, ctypes.byref(launches), ctypes.byref(timed), ctypes.byref(ms)))
+    return launches.value, timed.value, ms.value
+
+
+def ka_sim_path(s: Sim) -> int:
+    p = ctypes.c_int()
+    _check(load().ka_sim_path(s.handle, ctypes.byref(p)))
+    return p.value
+
+
+def ka_free(s: Sim) -> None:
+    s.free()
+
+
+def ka_last_error() -> str:
+    msg = load().ka_last_error()
+    return msg.decode() if msg else ""
+
+
+# ------------------------------------------------------------------------------ host helpers
+def k_from_rho(N: int, rho: float) -> int:
+    """Particle number the library uses for density rho: floor(rho*N + 1/2)."""
+    import math
+    return int(math.floor(float(rho) * float(N) + 0.5))
+
+
+def derived_observables(N: int, K: int, overlap, persistence):
+    """Replica averages of the integer counts (Sec. 2.2): q_b = (overlap_b/N - r^2)/(r(1-r))
+    with r = K/N, C = mean q_b, chi4 = N*(mean q_b^2 - (mean q_b)^2), and the mean
+    persistence fraction P = mean persistence_b / K.  Rows of a [n_obs, R] array give one
+    value per observation time."""
+    ov = np.atleast_2d(np.asarray(overlap, dtype=np.float64))
+    pe = np.atleast_2d(np.asarray(persistence, dtype=np.float64))
+    r = K / N
+    if 0 < K < N:
+        q = (ov / N - r * r) / (r * (1.0 - r))
+        C = q.mean(axis=1)
+        chi4 = N * ((q * q).mean(axis=1) - q.mean(axis=1) ** 2)
+    else:
+        C = np.full(ov.shape[0], np.nan)
+        chi4 = np.full(ov.shape[0], np.nan)
+    P = pe.mean(axis=1) / K if K > 0 else np.full(pe.shape[0], np.nan)
+    return C, chi4, P
+
+
+def log_time_grid(t_max: int, per_decade: int = 10) -> list[int]:
+    """0 and the distinct floor(10^(k/per_decade)) <= t_max: a log-spaced observation grid."""
+    import math
+    out = {0}
+    k = 0
+    while True:
+        v = int(math.floor(10.0 ** (k / per_decade)))
+        if v > t_max:
+            break
+        out.add(v)
+        k += 1
+    return sorted(out)

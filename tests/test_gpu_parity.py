@@ -1,0 +1,184 @@
+"""GPU parity: the HIP path (through the C ABI) against the oracle, bit for bit.
+
+The state is integer bit data and the observables are integer counts, so the bar is exact
+equality: packed occupations n, the t=0 copy n0, the moved-ever mask f, and the per-replica
+density / overlap / persistence counts.  Cases span both kernel paths (one launch per
+class pass over global memory, and the LDS-resident sweep loop), word layouts with one and
+two words per thread (R = 64, 128, 192, 256, 320), lattices whose side is not a power of
+two, random regular graphs of degree 3..6, every activation number m, and the degenerate
+particle numbers K = 0, 1, N-1, N.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_05155_amd import ka
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+def _state_equal(sim, orc):
+    n, n0, f, t = ka.ka_get_state(sim)
+    assert t == orc.t
+    from oracle import oracle as o
+    assert np.array_equal(n0, o.pack(orc.occ0)), "n0 differs"
+    assert np.array_equal(n, o.pack(orc.occ)), "n differs"
+    assert np.array_equal(f, o.pack(orc.moved)), "f differs"
+
+
+def _observe_equal(sim, orc):
+    t, dens, ov, pers = ka.ka_observe(sim)
+    odens, oov, opers = orc.observe()
+    assert t == orc.t
+    assert np.array_equal(dens, odens) and np.array_equal(ov, oov) and np.array_equal(pers, opers)
+
+
+def _check_case(oracle, lib_graph, or_graph, m, K, seed, R, chunks, path):
+    _say(f"N={or_graph.N} z={or_graph.z} m={m} K={K} R={R} path={path} chunks={chunks}")
+    sim = ka.ka_init_k(lib_graph, m, K, seed, R)
+    if path:
+        try:
+            ka.ka_set_option(sim, ka.KA_OPT_PATH, path)
+        except ka.KaError:
+            sim.free()
+            pytest.skip("this instance does not fit the LDS-resident path on this device")
+    orc = oracle.Sim(or_graph, m, K, seed, range(R))
+    _state_equal(sim, orc)
+    _observe_equal(sim, orc)
+    for n in chunks:
+        ka.ka_sweep(sim, n)
+        orc.sweep(n)
+        _state_equal(sim, orc)
+        _observe_equal(sim, orc)
+    sim.free()
+
+
+LATTICE_CASES = [
+    # d, L, m, rho, R
+    (2, 4, 2, 0.5, 64),
+    (2, 8, 0, 0.3, 64),
+    (2, 8, 3, 0.6, 128),
+    (2, 12, 1, 0.55, 192),
+    (2, 12, 2, 0.7, 320),
+    (2, 64, 2, 0.7, 64),
+    (2, 64, 2, 0.85, 256),
+    (3, 4, 3, 0.6, 64),
+    (3, 8, 3, 0.8, 128),
+    (3, 8, 5, 0.5, 64),
+    (3, 12, 2, 0.6, 192),
+    (3, 16, 3, 0.85, 256),
+]
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("d,L,m,rho,R", LATTICE_CASES)
+def test_lattice_parity(oracle, d, L, m, rho, R, path):
+    g = ka.ka_graph_lattice(d, L)
+    og = oracle.lattice(d, L)
+    K = oracle.k_from_rho(og.N, rho)
+    _check_case(oracle, g, og, m, K, 1234 + L, R, [1, 2, 4], path)
+
+
+RRG_CASES = [
+    # N, z, m, rho, R
+    (64, 3, 1, 0.5, 64),
+    (100, 4, 2, 0.6, 128),
+    (512, 5, 3, 0.7, 64),
+    (300, 6, 3, 0.8, 256),
+    (300, 6, 0, 0.4, 64),
+    (2000, 4, 2, 0.65, 192),
+]
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("N,z,m,rho,R", RRG_CASES)
+def test_rrg_parity(oracle, N, z, m, rho, R, path):
+    g = ka.ka_graph_rrg(N, z, 17)
+    oadj, _ = oracle.rrg_adjacency(N, z, 17)
+    og = oracle.graph_from_adjacency(oadj)
+    K = oracle.k_from_rho(N, rho)
+    _check_case(oracle, g, og, m, K, 99 + N, R, [1, 3, 5], path)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_degenerate_particle_numbers(oracle, path):
+    g = ka.ka_graph_lattice(2, 8)
+    og = oracle.lattice(2, 8)
+    for K in (0, 1, og.N - 1, og.N):
+        for m in (0, 2, 3):
+            _check_case(oracle, g, og, m, K, 5, 64, [3], path)
+
+
+def test_every_m_both_geometries(oracle):
+    for d, L in [(2, 8), (3, 8)]:
+        g = ka.ka_graph_lattice(d, L)
+        og = oracle.lattice(d, L)
+        for m in range(og.z):
+            _check_case(oracle, g, og, m, oracle.k_from_rho(og.N, 0.6), 3 + m, 128, [2], 1)
+
+
+@pytest.mark.parametrize("path", [1, 2])
+def test_run_observation_grid(oracle, path):
+    """ka_run records observations on the device; rows must equal the oracle's counts."""
+    g = ka.ka_graph_lattice(2, 16)
+    og = oracle.lattice(2, 16)
+    K = oracle.k_from_rho(og.N, 0.7)
+    _say(f"ka_run grid path={path}")
+    sim = ka.ka_init_k(g, 2, K, 77, 128)
+    ka.ka_set_option(sim, ka.KA_OPT_PATH, path)
+    times = [0, 0, 1, 2, 3, 5, 8, 8, 13, 21]
+    dens, ov, pers = ka.ka_run(sim, times)
+    orc = oracle.Sim(og, 2, K, 77, range(128))
+    for q, t in enumerate(times):
+        orc.sweep(t - orc.t)
+        od, oo, op = orc.observe()
+        assert np.array_equal(dens[q], od) and np.array_equal(ov[q], oo) and np.array_equal(pers[q], op), q
+    assert sim.t == 21
+    _state_equal(sim, orc)
+
+
+def test_paths_agree_and_split_invariance(oracle):
+    g = ka.ka_graph_lattice(3, 12)
+    _say("paths agree 3D L=12")
+    a = ka.ka_init(g, 3, 0.75, 8, 256)
+    ka.ka_set_option(a, ka.KA_OPT_PATH, 1)
+    ka.ka_sweep(a, 7)
+    b = ka.ka_init(g, 3, 0.75, 8, 256)
+    ka.ka_set_option(b, ka.KA_OPT_PATH, 2)
+    ka.ka_sweep(b, 3)
+    ka.ka_sweep(b, 4)
+    sa, sb = ka.ka_get_state(a), ka.ka_get_state(b)
+    for x, y in zip(sa, sb):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_set_state_resume(oracle):
+    """Checkpoint/resume: a state put back with ka_set_state continues exactly."""
+    g = ka.ka_graph_lattice(2, 12)
+    og = oracle.lattice(2, 12)
+    K = oracle.k_from_rho(og.N, 0.6)
+    _say("set_state resume")
+    orc = oracle.Sim(og, 2, K, 4, range(128))
+    orc.sweep(5)
+    sim = ka.ka_init_k(g, 2, K, 4, 128)
+    ka.ka_set_state(sim, oracle.pack(orc.occ), oracle.pack(orc.occ0), oracle.pack(orc.moved), orc.t)
+    ka.ka_sweep(sim, 6)
+    orc.sweep(6)
+    _state_equal(sim, orc)
+    _observe_equal(sim, orc)
+
+
+def test_replica_subset_independence(oracle):
+    """Replica b's trajectory does not depend on how many replicas run beside it."""
+    g = ka.ka_graph_lattice(2, 16)
+    _say("replica subset")
+    small = ka.ka_init(g, 2, 0.7, 3, 64)
+    big = ka.ka_init(g, 2, 0.7, 3, 256)
+    ka.ka_sweep(small, 9)
+    ka.ka_sweep(big, 9)
+    ns = ka.ka_get_state(small)[0]
+    nb = ka.ka_get_state(big)[0]
+    assert np.array_equal(ns[0], nb[0])

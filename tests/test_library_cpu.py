@@ -1,0 +1,91 @@
+"""Host-side checks of libka that need no GPU: the shared library loads and exports every
+symbol include/ka.h declares; its graph builders (lattice, random regular graph, any
+adjacency) and edge classes equal the oracle's, which are built by separate code; argument
+validation returns the documented error codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1710_05155_amd import ka
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_header_symbols_exported():
+    with open(os.path.join(ROOT, "include", "ka.h")) as fh:
+        header = fh.read()
+    declared = set(re.findall(r"\b(ka_[a-z_]+)\s*\(", header))
+    assert declared == set(ka.SYMBOLS)
+    lib = ctypes.CDLL(ka.LIB_PATH)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("d,L", [(2, 4), (2, 12), (2, 64), (3, 4), (3, 8), (3, 20)])
+def test_lattice_graph_matches_oracle(oracle, d, L):
+    g = ka.ka_graph_lattice(d, L)
+    og = oracle.lattice(d, L)
+    assert (g.N, g.z, g.E, g.C) == (og.N, og.z, og.E, og.C)
+    adj, eu, ev, ec = ka.ka_graph_export(g)
+    assert np.array_equal(adj, og.adj)
+    assert np.array_equal(eu, og.eu) and np.array_equal(ev, og.ev) and np.array_equal(ec, og.ecls)
+
+
+@pytest.mark.parametrize("N,z,seed", [(64, 3, 1), (100, 4, 7), (512, 5, 3), (300, 6, 11), (1 << 14, 4, 1),
+                                      (1 << 12, 5, 2)])
+def test_rrg_matches_oracle(oracle, N, z, seed):
+    g = ka.ka_graph_rrg(N, z, seed)
+    oadj, _ = oracle.rrg_adjacency(N, z, seed)
+    og = oracle.graph_from_adjacency(oadj)
+    adj, eu, ev, ec = ka.ka_graph_export(g)
+    assert np.array_equal(adj, oadj)
+    assert np.array_equal(eu, og.eu) and np.array_equal(ev, og.ev) and np.array_equal(ec, og.ecls)
+    assert g.C == og.C
+
+
+def test_from_adjacency_matches_oracle_and_keeps_row_order(oracle):
+    oadj, _ = oracle.rrg_adjacency(200, 4, 5)
+    rng = np.random.default_rng(0)
+    shuffled = np.array([rng.permutation(row) for row in oadj], dtype=np.int32)
+    g = ka.ka_graph_from_adjacency(shuffled)
+    og = oracle.graph_from_adjacency(shuffled)
+    adj, eu, ev, ec = ka.ka_graph_export(g)
+    assert np.array_equal(adj, shuffled)
+    assert np.array_equal(eu, og.eu) and np.array_equal(ev, og.ev) and np.array_equal(ec, og.ecls)
+
+
+def test_argument_errors():
+    with pytest.raises(ka.KaError) as e:
+        ka.ka_graph_lattice(2, 6)
+    assert e.value.code == ka.KA_EINVAL
+    with pytest.raises(ka.KaError):
+        ka.ka_graph_lattice(4, 8)
+    with pytest.raises(ka.KaError):
+        ka.ka_graph_rrg(5, 3, 1)           # N*z odd
+    with pytest.raises(ka.KaError):
+        ka.ka_graph_rrg(100, 7, 1)         # z out of range
+    bad = np.array([[1, 2, 3], [0, 2, 3], [0, 1, 3], [0, 1, 1]], dtype=np.int32)
+    with pytest.raises(ka.KaError):
+        ka.ka_graph_from_adjacency(bad)
+    g = ka.ka_graph_lattice(2, 8)
+    for m, R, rho in [(4, 64, 0.5), (-1, 64, 0.5), (2, 100, 0.5), (2, 0, 0.5), (2, 64, 1.5)]:
+        with pytest.raises(ka.KaError) as e:
+            ka.ka_init(g, m, rho, 1, R)
+        assert e.value.code == ka.KA_EINVAL
+
+
+def test_footprint():
+    g = ka.ka_graph_lattice(3, 128)
+    fp = ka.ka_footprint(g, 256)
+    assert fp >= 3 * 128 ** 3 * 4 * 8
+    r = ka.ka_graph_rrg(1 << 12, 4, 1)
+    assert ka.ka_footprint(r, 64) > 3 * (1 << 12) * 8 + (1 << 12) * 4 * 4
+
+
+def test_log_time_grid():
+    grid = ka.log_time_grid(10_000)
+    assert grid[0] == 0 and grid[-1] == 10_000 and len(grid) == 38
+    assert grid[:8] == [0, 1, 2, 3, 5, 6, 7, 10]
