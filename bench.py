@@ -98,6 +98,11 @@ def main():
     ap.add_argument("--timing-every", type=int, default=16,
                     help="bracket every k-th class-pass launch with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sweeps", type=int, default=None,
+                    help="override the sweeps per job (profiling runs only; the default is the workload's)")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB, so that a "
+                         "hardware-counter run can scale HBM byte counters by a kernel of known traffic")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the replica planes of a job shard across GPUs "
@@ -115,7 +120,17 @@ def main():
         g = ka.ka_graph_lattice(w["d"], w["L"])
     else:
         g = ka.ka_graph_rrg(w["N"], w["z"], w["graph_seed"])
+    if args.sweeps is not None:
+        w = dict(w, sweeps=args.sweeps)
     N, R, sweeps = g.N, w["R"], w["sweeps"]
+    if args.calibrate_copy_mib > 0:
+        nbytes = args.calibrate_copy_mib << 20
+        src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read + {nbytes} bytes written")
+        del src, dst
     W = R // 64
     grid = obs_grid(w)
 

@@ -529,7 +529,7 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t)
     a.nsub = s->lcls.nsub;
     for (int q = 0; q < a.nsub; ++q) a.sub[q] = s->lcls.sub[c][q];
     a.planes = s->planes;
-    const int per_plane = a.nsub * s->geom.P;
+    const int per_plane = a.nsub * 64 * ((s->geom.P + 63) / 64);  // whole 64-position chunks
     a.blocks_per_plane = (per_plane + 255) / 256;
     a.t = t;
     a.c = (uint32_t)c;

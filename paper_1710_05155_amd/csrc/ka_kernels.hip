@@ -412,6 +412,10 @@ __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int32_t *adj,
 // ------------------------------------------------------------------------------------
 // Global-memory class pass kernels: one launch per (class, sweep), all planes at once.
 // ------------------------------------------------------------------------------------
+// Thread order: a wave covers 64 consecutive positions of one lower-endpoint sublattice
+// (coalesced 64 x 16 B loads); consecutive waves cover the class's other lower-endpoint
+// sublattices at the same positions, so the neighbour sublattices they share are fetched
+// once and then served from L2 (together with the XCD-contiguous block order).
 template <int D, int MU, int WPT>
 __global__ __launch_bounds__(kPassBlock) void k_pass_lattice(PassLattice a, int m)
 {
@@ -419,10 +423,12 @@ __global__ __launch_bounds__(kPassBlock) void k_pass_lattice(PassLattice a, int 
   const int plane = lin / a.blocks_per_plane;
   const int blk = lin - plane * a.blocks_per_plane;
   const int gid = blk * kPassBlock + (int)threadIdx.x;
-  const int P = a.g.P;
-  if (gid >= a.nsub * P) return;
-  const int q = gid / P;
-  const int pos = gid - q * P;
+  const int span = a.nsub * 64;            // threads per 64-position chunk
+  const int chunk = gid / span;
+  const int rem = gid - chunk * span;
+  const int q = rem >> 6;
+  const int pos = chunk * 64 + (rem & 63);
+  if (pos >= a.g.P) return;
   const size_t off = (size_t)plane * (size_t)a.g.N * WPT;
   lattice_edge<D, MU, WPT>(a.n + off, a.f + off, a.g, a.sub[q], pos, plane, m, a.t, a.c,
                            a.key0, a.key1);
