@@ -56,6 +56,28 @@ def class_pass_bytes(w, N, W):
     return None
 
 
+def measured_traffic(kernel_sources, counters_file):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the
+    kernel sources no longer hash to the ones the counters were taken with."""
+    import hashlib
+    try:
+        kv = {}
+        with open(counters_file) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for path in kernel_sources:
+            with open(path, "rb") as fh:
+                h.update(fh.read())
+        if h.hexdigest() != kv.get("source_sha256"):
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def obs_grid(w):
     from paper_1710_05155_amd import ka
     if "obs_every" in w:
@@ -95,7 +117,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cubic128", choices=sorted(WORKLOADS))
-    ap.add_argument("--timing-every", type=int, default=16,
+    ap.add_argument("--timing-every", type=int, default=64,
                     help="bracket every k-th class-pass launch with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweeps", type=int, default=None,
@@ -199,8 +221,13 @@ def main():
     if path == 1 and pass_timed > 0 and B:
         avg_s = pass_ms_total / pass_timed / 1000.0
         achieved = B / avg_s / 1e9
+        csrc = os.path.join(ROOT, "paper_1710_05155_amd", "csrc")
+        traffic = None
+        if args.workload == "cubic128":
+            traffic = measured_traffic([os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")],
+                                       os.path.join(ROOT, "profiles", "k_pass_lattice_cubic128.counters.txt"))
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                              "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                               "kernel": "k_pass_lattice", "avg_launch_us": avg_s * 1e6,
                               "bytes_per_launch": B, "timed_launches": pass_timed}
     if not args.no_cpu_baseline:

@@ -10,6 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libka.so")
 ARCH = os.environ.get("KA_OFFLOAD_ARCH", "gfx950")
+SOURCES = ("ka_pass.hip", "ka_lds.hip", "ka_batch.hip", "ka_host.cpp")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 # No packed-FP32 instructions in any device code.
@@ -33,12 +34,13 @@ def build(verbose: bool = False) -> str:
     hipcc = _hipcc()
     bdir = os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
-    k_obj = os.path.join(bdir, "ka_kernels.o")
-    h_obj = os.path.join(bdir, "ka_host.o")
-    _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ka_kernels.hip"), "-o", k_obj], verbose)
-    _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, "ka_host.cpp"), "-o", h_obj], verbose)
+    objs = []
+    for src in SOURCES:
+        obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+        _run([hipcc, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj], verbose)
+        objs.append(obj)
     tmp = LIB + ".tmp"
-    _run([hipcc, *DEVICE, "-shared", "-fPIC", k_obj, h_obj, "-o", tmp], verbose)
+    _run([hipcc, *DEVICE, "-shared", "-fPIC", *objs, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 

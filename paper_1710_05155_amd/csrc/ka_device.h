@@ -1,0 +1,426 @@
+// ka_device.h -- device-side building blocks shared by the libka kernels.
+//
+// Method: Boccagna, arXiv 1710.05155.  The state of 64 replicas of one site is one 64-bit
+// word (Sec. 3.1, multispin coding).  An edge (i, j) is updated for all replicas of a word
+// at once with bitwise logic (Sec. 3.2): A_k = "at most m occupied neighbours of k other
+// than the partner" per replica, computed with a bit-sliced adder (one bit of the sum per
+// word, every replica in its own bit lane) and a comparison with m; the exchange mask is
+//     d = (n_i ^ n_j) & A_i & A_j & r,   n_i ^= d, n_j ^= d, f_i |= d, f_j |= d,
+// where r holds the per-replica Bernoulli(1/2) acceptance bits from Philox4x32-10.  This
+// equals the paper's Table 1 update with s_i = s_{i4} & s_{j5}, s_j = s_{j4} & s_{i5}
+// (Sec. 3.2): a particle at i may hop to an empty j iff i has at most m occupied
+// neighbours (j empty) and j at most m+1 (i occupied), i.e. both counts that exclude the
+// partner are at most m.  f marks sites whose occupation ever changed (persistence).
+//
+// All hot-path work is integer bit logic: there is no dense contraction, so no MFMA.
+#pragma once
+
+#include "ka_internal.h"
+
+namespace ka {
+namespace dev {
+
+
+// ------------------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The round keys depend only on the
+// seed, so they stay in scalar registers; each round is two 32x32->64 multiplies and xors.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const u64 p0 = (u64)0xD2511F53u * (u64)c.x;
+    const u64 p1 = (u64)0xCD9E8D57u * (u64)c.z;
+    uint4 y;
+    y.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    y.y = (uint32_t)p1;
+    y.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    y.w = (uint32_t)p0;
+    c = y;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return c;
+}
+
+__device__ __forceinline__ u64 lo_half(uint4 o) { return (u64)o.x | ((u64)o.y << 32); }
+__device__ __forceinline__ u64 hi_half(uint4 o) { return (u64)o.z | ((u64)o.w << 32); }
+
+// Acceptance words of the WPT words of plane `plane` for edge e of class c in sweep t:
+// word w uses half (w & 1) of Philox(t, c, e, w >> 1).
+template <int WPT>
+__device__ __forceinline__ void accept_words(uint32_t t, uint32_t c, uint32_t e, int plane,
+                                             uint32_t k0, uint32_t k1, u64 (&r)[WPT])
+{
+  if constexpr (WPT == 2) {
+    const uint4 o = philox10(make_uint4(t, c, e, (uint32_t)plane), k0, k1);
+    r[0] = lo_half(o);
+    r[1] = hi_half(o);
+  } else {
+    const uint4 o = philox10(make_uint4(t, c, e, (uint32_t)plane >> 1), k0, k1);
+    r[0] = (plane & 1) ? hi_half(o) : lo_half(o);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Element = the WPT words of one site in one plane.
+// ------------------------------------------------------------------------------------
+template <int WPT>
+struct Elem {
+  u64 w[WPT];
+};
+
+template <int WPT>
+__device__ __forceinline__ Elem<WPT> ld(const u64 *base, int idx)
+{
+  Elem<WPT> e;
+  if constexpr (WPT == 2) {
+    const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(base)[idx];
+    e.w[0] = v.x;
+    e.w[1] = v.y;
+  } else {
+    e.w[0] = base[idx];
+  }
+  return e;
+}
+
+template <int WPT>
+__device__ __forceinline__ void st(u64 *base, int idx, const Elem<WPT> &e)
+{
+  if constexpr (WPT == 2) {
+    ulonglong2 v;
+    v.x = e.w[0];
+    v.y = e.w[1];
+    reinterpret_cast<ulonglong2 *>(base)[idx] = v;
+  } else {
+    base[idx] = e.w[0];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Bit-sliced neighbour count and threshold (replaces the paper's Karnaugh subset-OR forms
+// of Sec. 3.2 for general z and m): (s2 s1 s0) is, in every bit lane, the number of set
+// inputs; at_most(m) is the per-lane predicate "sum <= m".
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void full_add(u64 a, u64 b, u64 c, u64 &s, u64 &carry)
+{
+  const u64 t = a ^ b;
+  s = t ^ c;
+  carry = (t & c) | (~t & a);
+}
+
+template <int K>
+__device__ __forceinline__ void bitsum(const u64 (&x)[K], u64 &s0, u64 &s1, u64 &s2)
+{
+  static_assert(K >= 3 && K <= 7, "bit-sliced sum supports 3..7 inputs");
+  if constexpr (K == 3) {
+    full_add(x[0], x[1], x[2], s0, s1);
+    s2 = 0;
+  } else if constexpr (K == 4) {
+    u64 a0, a1;
+    full_add(x[0], x[1], x[2], a0, a1);
+    s0 = a0 ^ x[3];
+    const u64 b1 = a0 & x[3];
+    s1 = a1 ^ b1;
+    s2 = a1 & b1;
+  } else if constexpr (K == 5) {
+    u64 a0, a1, b1;
+    full_add(x[0], x[1], x[2], a0, a1);
+    full_add(x[3], x[4], a0, s0, b1);
+    s1 = a1 ^ b1;
+    s2 = a1 & b1;
+  } else if constexpr (K == 6) {
+    u64 a0, a1, b0, b1;
+    full_add(x[0], x[1], x[2], a0, a1);
+    full_add(x[3], x[4], x[5], b0, b1);
+    s0 = a0 ^ b0;
+    const u64 c1 = a0 & b0;
+    full_add(a1, b1, c1, s1, s2);
+  } else {
+    u64 a0, a1, b0, b1, c1;
+    full_add(x[0], x[1], x[2], a0, a1);
+    full_add(x[3], x[4], x[5], b0, b1);
+    full_add(a0, b0, x[6], s0, c1);
+    full_add(a1, b1, c1, s1, s2);
+  }
+}
+
+// m is wave-uniform, so the branches below are scalar.
+__device__ __forceinline__ u64 at_most(u64 s0, u64 s1, u64 s2, int m)
+{
+  if (m >= 7) return ~0ull;
+  u64 gt = 0, eq = ~0ull;
+  if (m & 4) {
+    eq = s2;
+  } else {
+    gt = s2;
+    eq = ~s2;
+  }
+  if (m & 2) {
+    eq &= s1;
+  } else {
+    gt |= eq & s1;
+    eq &= ~s1;
+  }
+  if (!(m & 1)) gt |= eq & s0;
+  return ~gt;
+}
+
+template <int K>
+__device__ __forceinline__ u64 activity(const u64 (&x)[K], int m)
+{
+  u64 s0, s1, s2;
+  bitsum<K>(x, s0, s1, s2);
+  return at_most(s0, s1, s2, m);
+}
+
+// Exchange for one element pair; returns d per word.
+template <int K, int WPT>
+__device__ __forceinline__ void exchange(Elem<WPT> &ni, Elem<WPT> &nj, const Elem<WPT> (&xi)[K],
+                                         const Elem<WPT> (&xj)[K], const u64 (&r)[WPT], int m,
+                                         u64 (&d)[WPT])
+{
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) {
+    u64 ai[K], aj[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      ai[k] = xi[k].w[w];
+      aj[k] = xj[k].w[w];
+    }
+    const u64 Ai = activity<K>(ai, m);
+    const u64 Aj = activity<K>(aj, m);
+    d[w] = (ni.w[w] ^ nj.w[w]) & Ai & Aj & r[w];
+    ni.w[w] ^= d[w];
+    nj.w[w] ^= d[w];
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Workgroup -> tile mapping aware of the 8 XCDs: the hardware hands consecutive
+// workgroups to XCDs round-robin; renumber so that each XCD gets one contiguous range of
+// tiles, whose stencil halos then meet in that XCD's own L2.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_remap(int b, int nb)
+{
+  const int per = nb >> 3, rem = nb & 7;
+  const int x = b & 7, q = b >> 3;
+  return (x < rem) ? x * (per + 1) + q : rem * (per + 1) + (x - rem) * per + q;
+}
+
+// ------------------------------------------------------------------------------------
+// Lattice indexing in the sublattice layout (see ka_internal.h).
+// ------------------------------------------------------------------------------------
+struct Site {
+  int a[3];  // residues x_nu mod 4
+  int p[3];  // block coordinates x_nu / 4
+  int idx;   // element index sub*P + pos
+};
+
+__device__ __forceinline__ Site decode(const LatticeGeom &g, int D, int sub, int pos)
+{
+  Site s;
+  s.a[0] = sub & 3;
+  s.a[1] = (sub >> 2) & 3;
+  s.a[2] = (sub >> 4) & 3;
+  s.p[0] = pos % g.Q;
+  const int rest = pos / g.Q;
+  if (D == 3) {
+    s.p[1] = rest % g.Q;
+    s.p[2] = rest / g.Q;
+  } else {
+    s.p[1] = rest;
+    s.p[2] = 0;
+  }
+  s.idx = sub * g.P + pos;
+  return s;
+}
+
+__device__ __forceinline__ int qpow(const LatticeGeom &g, int nu)
+{
+  return nu == 0 ? 1 : (nu == 1 ? g.Q : g.Q * g.Q);
+}
+
+// element index of s + e_nu
+__device__ __forceinline__ int step_up(const LatticeGeom &g, const Site &s, int nu)
+{
+  const int sub_stride = g.P << (2 * nu);
+  if (s.a[nu] < 3) return s.idx + sub_stride;
+  const int ps = qpow(g, nu);
+  return s.idx - 3 * sub_stride + ((s.p[nu] + 1 < g.Q) ? ps : -(g.Q - 1) * ps);
+}
+
+// element index of s - e_nu
+__device__ __forceinline__ int step_dn(const LatticeGeom &g, const Site &s, int nu)
+{
+  const int sub_stride = g.P << (2 * nu);
+  if (s.a[nu] > 0) return s.idx - sub_stride;
+  const int ps = qpow(g, nu);
+  return s.idx + 3 * sub_stride + ((s.p[nu] > 0) ? -ps : (g.Q - 1) * ps);
+}
+
+__device__ __forceinline__ Site move_up(const LatticeGeom &g, const Site &s, int nu)
+{
+  Site t = s;
+  t.idx = step_up(g, s, nu);
+  if (s.a[nu] < 3) {
+    t.a[nu] = s.a[nu] + 1;
+  } else {
+    t.a[nu] = 0;
+    t.p[nu] = (s.p[nu] + 1 < g.Q) ? s.p[nu] + 1 : 0;
+  }
+  return t;
+}
+
+__device__ __forceinline__ int canonical(const LatticeGeom &g, int D, const Site &s)
+{
+  const int x0 = 4 * s.p[0] + s.a[0];
+  const int x1 = 4 * s.p[1] + s.a[1];
+  if (D == 2) return x0 + g.L * x1;
+  const int x2 = 4 * s.p[2] + s.a[2];
+  return x0 + g.L * (x1 + g.L * x2);
+}
+
+// Element indices of the 2D-1 neighbours of i other than j = i + e_MU, and of j other than i.
+template <int D, int MU>
+__device__ __forceinline__ void lattice_stencil(const LatticeGeom &g, const Site &si,
+                                                const Site &sj, int (&ii)[2 * D - 1],
+                                                int (&jj)[2 * D - 1])
+{
+  int q = 0;
+#pragma unroll
+  for (int nu = 0; nu < D; ++nu) {
+    if (nu == MU) {
+      ii[q] = step_dn(g, si, nu);
+      jj[q] = step_up(g, sj, nu);
+      ++q;
+    } else {
+      ii[q] = step_up(g, si, nu);
+      jj[q] = step_up(g, sj, nu);
+      ++q;
+      ii[q] = step_dn(g, si, nu);
+      jj[q] = step_dn(g, sj, nu);
+      ++q;
+    }
+  }
+}
+
+// One lattice edge on the plane at base (global memory or LDS); shared by both paths.
+template <int D, int MU, int WPT>
+__device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom &g, int sub,
+                                             int pos, int plane, int m, uint32_t t, uint32_t c,
+                                             uint32_t k0, uint32_t k1)
+{
+  constexpr int K = 2 * D - 1;
+  const Site si = decode(g, D, sub, pos);
+  const Site sj = move_up(g, si, MU);
+  int ii[K], jj[K];
+  lattice_stencil<D, MU>(g, si, sj, ii, jj);
+  Elem<WPT> ni = ld<WPT>(nb, si.idx);
+  Elem<WPT> nj = ld<WPT>(nb, sj.idx);
+  Elem<WPT> xi[K], xj[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    xi[k] = ld<WPT>(nb, ii[k]);
+    xj[k] = ld<WPT>(nb, jj[k]);
+  }
+  const uint32_t e = (uint32_t)canonical(g, D, si) * (uint32_t)D + (uint32_t)MU;
+  u64 r[WPT];
+  accept_words<WPT>(t, c, e, plane, k0, k1, r);
+  u64 d[WPT];
+  exchange<K, WPT>(ni, nj, xi, xj, r, m, d);
+  u64 any = 0;
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) any |= d[w];
+  if (any) {
+    st<WPT>(nb, si.idx, ni);
+    st<WPT>(nb, sj.idx, nj);
+    Elem<WPT> fi = ld<WPT>(fb, si.idx);
+    Elem<WPT> fj = ld<WPT>(fb, sj.idx);
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) {
+      fi.w[w] |= d[w];
+      fj.w[w] |= d[w];
+    }
+    st<WPT>(fb, si.idx, fi);
+    st<WPT>(fb, sj.idx, fj);
+  }
+}
+
+// One general-graph edge (u, v, e).  The 2z neighbour words are gathered; the partner's
+// word is picked out of the other endpoint's row and zeroed there, so the bit-sliced sum
+// over z inputs counts exactly the z-1 neighbours other than the partner.
+template <int Z, int WPT>
+__device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int32_t *adj, int4 E,
+                                           int plane, int m, uint32_t t, uint32_t c,
+                                           uint32_t k0, uint32_t k1)
+{
+  const int u = E.x, v = E.y;
+  int nu[Z], nv[Z];
+#pragma unroll
+  for (int q = 0; q < Z; ++q) {
+    nu[q] = adj[(size_t)u * Z + q];
+    nv[q] = adj[(size_t)v * Z + q];
+  }
+  Elem<WPT> xu[Z], xv[Z];
+#pragma unroll
+  for (int q = 0; q < Z; ++q) {
+    xu[q] = ld<WPT>(nb, nu[q]);
+    xv[q] = ld<WPT>(nb, nv[q]);
+  }
+  Elem<WPT> ni, nj;
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) {
+    ni.w[w] = 0;
+    nj.w[w] = 0;
+  }
+#pragma unroll
+  for (int q = 0; q < Z; ++q) {
+    const bool is_v = nu[q] == v;
+    const bool is_u = nv[q] == u;
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) {
+      nj.w[w] |= is_v ? xu[q].w[w] : 0ull;
+      xu[q].w[w] = is_v ? 0ull : xu[q].w[w];
+      ni.w[w] |= is_u ? xv[q].w[w] : 0ull;
+      xv[q].w[w] = is_u ? 0ull : xv[q].w[w];
+    }
+  }
+  u64 r[WPT];
+  accept_words<WPT>(t, c, (uint32_t)E.z, plane, k0, k1, r);
+  u64 d[WPT];
+  exchange<Z, WPT>(ni, nj, xu, xv, r, m, d);
+  u64 any = 0;
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) any |= d[w];
+  if (any) {
+    st<WPT>(nb, u, ni);
+    st<WPT>(nb, v, nj);
+    Elem<WPT> fu = ld<WPT>(fb, u);
+    Elem<WPT> fv = ld<WPT>(fb, v);
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) {
+      fu.w[w] |= d[w];
+      fv.w[w] |= d[w];
+    }
+    st<WPT>(fb, u, fu);
+    st<WPT>(fb, v, fv);
+  }
+}
+
+// ------------------------------------------------------------------------------------
+// Vertical (per-replica) population counts with wavefront ballots: lane l of the wave
+// accumulates, for replica bit l, the number of the wave's 64 sites whose bit l is set.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ void ballot_count(u64 x, unsigned &acc)
+{
+  const int lane = (int)__lane_id();
+#pragma unroll
+  for (int l = 0; l < 64; ++l) {
+    const unsigned c = (unsigned)__popcll(__ballot((int)((x >> l) & 1ull)));
+    acc += (lane == l) ? c : 0u;
+  }
+}
+
+}  // namespace dev
+}  // namespace ka

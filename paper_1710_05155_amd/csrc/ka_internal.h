@@ -117,3 +117,39 @@ size_t sweep_lds_bytes(int N, int wpt);
 int max_lds_bytes();
 
 }  // namespace ka
+
+namespace ka {
+
+// ------------------------------------------------------------------------------------
+// Batched execution of many instances: one step kernel applies one class pass to every
+// active member.  Member k is active for global steps s in [s_begin, s_end); at step s it
+// runs class (s - s_begin) mod C of its sweep t0 + (s - s_begin) / C.
+// ------------------------------------------------------------------------------------
+constexpr int kBatchMaxMembers = 1024;
+
+struct BatchMember {
+  u64 *n;
+  u64 *f;
+  const int32_t *adj;          // graphs: [N][z]
+  const int4 *edges;           // graphs: class-sorted (u, v, e, 0)
+  const int *class_start;      // graphs: [C+1]
+  int kind;                    // 0 lattice, 1 graph
+  int d, L, Q, P, N;           // lattice geometry (N for both)
+  int z, m, C, planes, wpt;
+  uint32_t key0, key1;
+  uint32_t t0;
+  int pad0;
+  long long s_begin, s_end;
+};
+
+struct BatchCtl {
+  long long step;              // global step the next step kernel executes
+  unsigned done;               // blocks finished in the current launch
+  int n_members;
+  int prefix[kBatchMaxMembers + 1];   // tile prefix over members for `step`
+};
+
+hipError_t launch_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int block, hipStream_t s);
+hipError_t launch_batch_step(BatchCtl *ctl, const BatchMember *mem, int block, int grid, hipStream_t s);
+
+}  // namespace ka

@@ -1,0 +1,212 @@
+// ka_lds.hip -- LDS-resident sweep loop for instances whose word plane fits in LDS (gfx950).
+//
+// Method: Boccagna, arXiv 1710.05155; the per-edge bit logic lives in ka_device.h.
+#include "ka_device.h"
+
+namespace ka {
+namespace {
+
+using namespace dev;
+
+constexpr int kLdsBlock = 1024;
+
+template <int WPT>
+__device__ void lds_observe(const SweepLds &a, const u64 *sn, const u64 *sf, int plane,
+                            int row, unsigned *cnt)
+{
+  const int tid = (int)threadIdx.x;
+  const int lane = (int)__lane_id();
+  const int wave = tid / 64, nw = (int)blockDim.x / 64;
+  for (int q = tid; q < 3 * 64 * WPT; q += (int)blockDim.x) cnt[q] = 0;
+  __syncthreads();
+  unsigned acc[3][WPT];
+#pragma unroll
+  for (int o = 0; o < 3; ++o)
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) acc[o][w] = 0;
+  const u64 *n0 = a.n0 + (size_t)plane * (size_t)a.N * WPT;
+  for (int base = wave * 64; base < a.N; base += nw * 64) {
+    const int idx = base + lane;
+    Elem<WPT> x, x0, xf;
+    if (idx < a.N) {
+      x = ld<WPT>(sn, idx);
+      xf = ld<WPT>(sf, idx);
+      x0 = ld<WPT>(n0, idx);
+    } else {
+#pragma unroll
+      for (int w = 0; w < WPT; ++w) x.w[w] = x0.w[w] = xf.w[w] = 0;
+    }
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) {
+      ballot_count(x.w[w], acc[0][w]);
+      ballot_count(x.w[w] & x0.w[w], acc[1][w]);
+      ballot_count(x0.w[w] & ~xf.w[w], acc[2][w]);
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < 3; ++o)
+#pragma unroll
+    for (int w = 0; w < WPT; ++w)
+      if (acc[o][w]) atomicAdd(&cnt[o * 64 * WPT + w * 64 + lane], acc[o][w]);
+  __syncthreads();
+  for (int q = tid; q < 3 * 64 * WPT; q += (int)blockDim.x) {
+    const int o = q / (64 * WPT), rr = q - o * 64 * WPT;
+    a.obs_out[((size_t)row * 3 + o) * a.R + (size_t)plane * 64 * WPT + rr] = cnt[q];
+  }
+  __syncthreads();
+}
+
+template <int WPT>
+__device__ void lds_load(const SweepLds &a, u64 *sn, u64 *sf, int plane)
+{
+  const size_t off = (size_t)plane * (size_t)a.N * WPT;
+  for (int q = (int)threadIdx.x; q < a.N * WPT; q += (int)blockDim.x) {
+    sn[q] = a.n[off + q];
+    sf[q] = a.f[off + q];
+  }
+  __syncthreads();
+}
+
+template <int WPT>
+__device__ void lds_store(const SweepLds &a, const u64 *sn, const u64 *sf, int plane)
+{
+  __syncthreads();
+  const size_t off = (size_t)plane * (size_t)a.N * WPT;
+  for (int q = (int)threadIdx.x; q < a.N * WPT; q += (int)blockDim.x) {
+    a.n[off + q] = sn[q];
+    a.f[off + q] = sf[q];
+  }
+}
+
+template <int WPT>
+__device__ void lds_observe_due(const SweepLds &a, const u64 *sn, const u64 *sf, int plane,
+                                int &qo, int64_t t_now, unsigned *cnt)
+{
+  while (qo < a.n_obs && a.obs_times[qo] == t_now) {
+    lds_observe<WPT>(a, sn, sf, plane, qo, cnt);
+    ++qo;
+  }
+}
+
+template <int D, int WPT>
+__global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int m)
+{
+  extern __shared__ u64 lds[];
+  __shared__ unsigned cnt[3 * 64 * WPT];
+  u64 *sn = lds;
+  u64 *sf = lds + (size_t)a.N * WPT;
+  const int plane = blockIdx.x;
+  lds_load<WPT>(a, sn, sf, plane);
+  int qo = 0;
+  lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)a.t0, cnt);
+  const int per_class = a.cls.nsub * a.g.P;
+  for (int s = 0; s < a.n_sweeps; ++s) {
+    const uint32_t t = a.t0 + (uint32_t)s;
+    for (int c = 0; c < a.C; ++c) {
+      const int mu = c >> 2;
+      for (int k = (int)threadIdx.x; k < per_class; k += (int)blockDim.x) {
+        const int q = k / a.g.P;
+        const int pos = k - q * a.g.P;
+        const int sub = a.cls.sub[c][q];
+        if (mu == 0)
+          lattice_edge<D, 0, WPT>(sn, sf, a.g, sub, pos, plane, m, t, (uint32_t)c, a.key0, a.key1);
+        else if (mu == 1)
+          lattice_edge<D, 1, WPT>(sn, sf, a.g, sub, pos, plane, m, t, (uint32_t)c, a.key0, a.key1);
+        else if constexpr (D == 3)
+          lattice_edge<D, 2, WPT>(sn, sf, a.g, sub, pos, plane, m, t, (uint32_t)c, a.key0, a.key1);
+      }
+      __syncthreads();
+    }
+    lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)t + 1, cnt);
+  }
+  lds_store<WPT>(a, sn, sf, plane);
+}
+
+template <int Z, int WPT>
+__global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_graph(SweepLds a, int m)
+{
+  extern __shared__ u64 lds[];
+  __shared__ unsigned cnt[3 * 64 * WPT];
+  u64 *sn = lds;
+  u64 *sf = lds + (size_t)a.N * WPT;
+  const int plane = blockIdx.x;
+  lds_load<WPT>(a, sn, sf, plane);
+  int qo = 0;
+  lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)a.t0, cnt);
+  for (int s = 0; s < a.n_sweeps; ++s) {
+    const uint32_t t = a.t0 + (uint32_t)s;
+    for (int c = 0; c < a.C; ++c) {
+      const int b0 = a.class_start[c], b1 = a.class_start[c + 1];
+      for (int k = b0 + (int)threadIdx.x; k < b1; k += (int)blockDim.x)
+        graph_edge<Z, WPT>(sn, sf, a.adj, a.edges[k], plane, m, t, (uint32_t)c, a.key0, a.key1);
+      __syncthreads();
+    }
+    lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)t + 1, cnt);
+  }
+  lds_store<WPT>(a, sn, sf, plane);
+}
+
+template <typename Kern>
+hipError_t set_lds(Kern k, size_t bytes)
+{
+  return hipFuncSetAttribute(reinterpret_cast<const void *>(k),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+}  // namespace
+
+size_t sweep_lds_bytes(int N, int wpt) { return (size_t)2 * (size_t)N * (size_t)wpt * 8u; }
+
+int max_lds_bytes()
+{
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+  return v;
+}
+
+hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, int wpt,
+                            size_t lds_bytes, hipStream_t s)
+{
+  const int planes = (a.R / 64) / wpt;
+  const dim3 grid((unsigned)planes);
+  const dim3 block(kLdsBlock);
+  hipError_t e = hipSuccess;
+#define KA_LDS_L(D, W)                                                            \
+  do {                                                                            \
+    e = set_lds(k_sweep_lds_lattice<D, W>, lds_bytes);                            \
+    if (e == hipSuccess)                                                          \
+      hipLaunchKernelGGL((k_sweep_lds_lattice<D, W>), grid, block, lds_bytes, s, a, m); \
+  } while (0)
+#define KA_LDS_G(Z, W)                                                            \
+  do {                                                                            \
+    e = set_lds(k_sweep_lds_graph<Z, W>, lds_bytes);                              \
+    if (e == hipSuccess)                                                          \
+      hipLaunchKernelGGL((k_sweep_lds_graph<Z, W>), grid, block, lds_bytes, s, a, m); \
+  } while (0)
+  if (lattice) {
+    if (a.g.d == 2) {
+      if (wpt == 2) KA_LDS_L(2, 2); else KA_LDS_L(2, 1);
+    } else {
+      if (wpt == 2) KA_LDS_L(3, 2); else KA_LDS_L(3, 1);
+    }
+  } else {
+    switch (zdeg * 4 + wpt) {
+      case 3 * 4 + 1: KA_LDS_G(3, 1); break;
+      case 3 * 4 + 2: KA_LDS_G(3, 2); break;
+      case 4 * 4 + 1: KA_LDS_G(4, 1); break;
+      case 4 * 4 + 2: KA_LDS_G(4, 2); break;
+      case 5 * 4 + 1: KA_LDS_G(5, 1); break;
+      case 5 * 4 + 2: KA_LDS_G(5, 2); break;
+      case 6 * 4 + 1: KA_LDS_G(6, 1); break;
+      case 6 * 4 + 2: KA_LDS_G(6, 2); break;
+      default: return hipErrorInvalidValue;
+    }
+  }
+#undef KA_LDS_L
+#undef KA_LDS_G
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+}  // namespace ka

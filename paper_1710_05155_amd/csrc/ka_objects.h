@@ -1,0 +1,65 @@
+// ka_objects.h -- the opaque objects behind the C ABI (include/ka.h), shared by the host
+// translation units of libka.
+#pragma once
+
+#include <stdint.h>
+
+#include <utility>
+#include <vector>
+
+#include "ka.h"
+#include "ka_internal.h"
+
+struct ka_graph {
+  int lattice = 0;  // 1: hypercubic lattice (d, L); 0: general z-regular graph
+  int d = 0, L = 0;
+  int64_t N = 0;
+  int z = 0;
+  int C = 0;
+  std::vector<int32_t> adj;            // [N][z]
+  std::vector<int32_t> eu, ev, ecls;   // canonical edges
+};
+
+struct ka_sim {
+  // graph summary
+  int lattice = 0;
+  int z = 0, C = 0;
+  int64_t N = 0;
+  ka::LatticeGeom geom{};
+  ka::LatticeClasses lcls{};
+  std::vector<int> class_start;   // general graphs: [C+1]
+  // parameters
+  int m = 0;
+  int64_t K = 0;
+  uint64_t seed = 0;
+  int R = 0, W = 0, wpt = 1, planes = 1;
+  int64_t t = 0;
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // device memory
+  ka::u64 *n = nullptr, *n0 = nullptr, *f = nullptr;
+  int32_t *adj = nullptr;
+  int4 *edges = nullptr;
+  int *class_start_d = nullptr;
+  ka::u64 *thr_u = nullptr;
+  long long *thr_i = nullptr;
+  int *err = nullptr;
+  unsigned long long *counts = nullptr;
+  size_t counts_cap = 0;
+  int64_t *obs_d = nullptr;
+  size_t obs_cap = 0;
+  // batch membership: while set, the sim is advanced by that batch only
+  struct ka_batch *batch = nullptr;
+  // options and timing
+  bool init_checked = false;
+  int path_opt = 0;
+  size_t lds_bytes = 0;
+  bool lds_fits = false;
+  int64_t timing_every = 0;
+  int64_t launches = 0;
+  int64_t timed = 0;
+  double timed_ms = 0.0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+  std::vector<hipEvent_t> event_pool;
+};
