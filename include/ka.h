@@ -146,7 +146,58 @@ int ka_timing(ka_sim *s, int64_t *launches, int64_t *timed, double *timed_ms);
 /* Path a ka_sweep would take now: 1 = global class passes, 2 = LDS-resident. */
 int ka_sim_path(const ka_sim *s, int *path);
 
+/* Release a sim.  A sim that is still a batch member is first run to the end of its
+ * batch work (see ka_batch_add). */
 void ka_free(ka_sim *s);
+
+/* ------------------------------------------------------------------------------------ */
+/* Batches: many sims advanced together.  One step kernel applies one class pass to every */
+/* active member; member k, added at global step s_k with n_k sweeps, runs class          */
+/* (s - s_k) mod C_k of its sweep t_k + (s - s_k) / C_k at step s, for s_k <= s <          */
+/* s_k + C_k*n_k.  The per-edge arithmetic and random counters are those of ka_sweep, so   */
+/* a member ends in exactly the state ka_sweep(n_k) would give it alone.  Steps advance on */
+/* the device, so the library replays a captured HIP graph of step kernels.               */
+/* ------------------------------------------------------------------------------------ */
+typedef struct ka_batch ka_batch;
+
+/* Batch with room for `capacity` members (1..1024), executing on hip_stream (NULL: a
+ * stream the library creates).  Members' own streams are ordered before their batch work. */
+int ka_batch_create(int capacity, void *hip_stream, ka_batch **out);
+
+/* Add sim s to advance by n_sweeps sweeps, starting at the next step enqueued.  The sim
+ * must be on the batch's device and in no other batch; until it is detached (ka_batch_poll,
+ * ka_batch_wait_all) every other call on it returns KA_ESTATE.  *slot receives its slot. */
+int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot);
+
+/* Enqueue n_steps step kernels (asynchronous).  The first call tunes the launch shape
+ * (workgroup size and number of persistent workgroups) on its first steps unless
+ * KA_BOPT_AUTOTUNE is 0. */
+int ka_batch_run(ka_batch *b, int64_t n_steps);
+
+/* Steps still to enqueue until every member's work is enqueued. */
+int ka_batch_steps_left(const ka_batch *b, int64_t *steps_left);
+
+/* Detach members whose work the device has completed (non-blocking); their slots are
+ * written to slots[0..*n_done) (at most max_slots) and their t advanced. */
+int ka_batch_poll(ka_batch *b, int *slots, int max_slots, int *n_done);
+
+/* Run every member to completion, wait, and detach all members. */
+int ka_batch_wait_all(ka_batch *b);
+
+/* Options: KA_BOPT_AUTOTUNE (1 default / 0), KA_BOPT_BLOCK (128, 256, 512; disables
+ * autotuning), KA_BOPT_GRID (persistent workgroups; disables autotuning),
+ * KA_BOPT_GRAPH_STEPS (step kernels per captured graph; 0 = plain launches). */
+#define KA_BOPT_AUTOTUNE 1
+#define KA_BOPT_BLOCK 2
+#define KA_BOPT_GRID 3
+#define KA_BOPT_GRAPH_STEPS 4
+int ka_batch_set_option(ka_batch *b, int option, int64_t value);
+
+/* Global step (enqueued), active members, and the launch shape in use. */
+int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *grid);
+
+/* Finish all members (as ka_batch_wait_all) and release the batch. */
+void ka_batch_free(ka_batch *b);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char *ka_last_error(void);

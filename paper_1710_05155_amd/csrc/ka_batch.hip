@@ -154,13 +154,19 @@ __device__ __forceinline__ void run_graph_tile(const BatchMember &mb, int local,
   }
 }
 
+// After the member table changed: set the member count and rebuild the work list of the
+// step the next step kernel executes.  The tile size is BLOCK of the step kernels that
+// follow, so this kernel is launched with the same BLOCK.
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_batch_prepare(BatchCtl *ctl, const BatchMember *mem)
+__global__ __launch_bounds__(BLOCK) void k_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int n)
 {
   __shared__ int scratch[BLOCK];
   const long long s = ctl->step;
-  build_prefix<BLOCK>(mem, ctl->n_members, s, ctl->prefix, scratch);
-  if (threadIdx.x == 0) ctl->done = 0;
+  build_prefix<BLOCK>(mem, n, s, ctl->prefix, scratch);
+  if (threadIdx.x == 0) {
+    ctl->n_members = n;
+    ctl->done = 0;
+  }
 }
 
 template <int BLOCK>
@@ -224,12 +230,13 @@ __global__ __launch_bounds__(BLOCK) void k_batch_step(BatchCtl *ctl, const Batch
 
 }  // namespace
 
-hipError_t launch_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int block, hipStream_t s)
+hipError_t launch_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int n_members, int block,
+                                hipStream_t s)
 {
   switch (block) {
-    case 128: hipLaunchKernelGGL((k_batch_prepare<128>), dim3(1), dim3(128), 0, s, ctl, mem); break;
-    case 256: hipLaunchKernelGGL((k_batch_prepare<256>), dim3(1), dim3(256), 0, s, ctl, mem); break;
-    case 512: hipLaunchKernelGGL((k_batch_prepare<512>), dim3(1), dim3(512), 0, s, ctl, mem); break;
+    case 128: hipLaunchKernelGGL((k_batch_prepare<128>), dim3(1), dim3(128), 0, s, ctl, mem, n_members); break;
+    case 256: hipLaunchKernelGGL((k_batch_prepare<256>), dim3(1), dim3(256), 0, s, ctl, mem, n_members); break;
+    case 512: hipLaunchKernelGGL((k_batch_prepare<512>), dim3(1), dim3(512), 0, s, ctl, mem, n_members); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -1,0 +1,464 @@
+// ka_batch_host.cpp -- host side of batched execution (include/ka.h, "Batches").
+//
+// A batch keeps a member table (pinned host copy + device copy) and a device control block
+// (global step, work-list prefix).  Step kernels advance the step themselves, so the host
+// only enqueues launches: whole captured graphs of step kernels, then single launches for
+// the remainder.  Progress events let ka_batch_poll detach finished members without
+// blocking.  Member descriptors never change while a member is active, and a slot is reused
+// only after its member's last step has completed on the device, so one pinned table and
+// whole-table asynchronous uploads are enough: a table that already holds members added
+// later is still correct for earlier steps, because a member is inactive outside
+// [s_begin, s_end).
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ka_objects.h"
+
+namespace {
+
+thread_local std::string g_batch_err;
+
+int bfail(int code, const char *fmt, ...)
+{
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  ka_set_error(buf);
+  return code;
+}
+
+int bhip(hipError_t e, const char *what)
+{
+  return bfail(KA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+struct Guard {
+  int prev = -1;
+  explicit Guard(int dev)
+  {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    else prev = -1;
+  }
+  ~Guard()
+  {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+}  // namespace
+
+struct ka_batch {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int capacity = 0;
+  int cus = 256;
+  ka::BatchMember *host_tab = nullptr;   // pinned
+  ka::BatchMember *d_tab = nullptr;
+  ka::BatchCtl *d_ctl = nullptr;
+  std::vector<ka_sim *> sims;            // per slot (nullptr = free)
+  std::vector<int64_t> sweeps;           // per slot
+  int n_members = 0;                     // highest used slot + 1
+  int64_t step = 0;                      // steps enqueued
+  int64_t done_step = 0;                 // steps known complete on the device
+  std::deque<std::pair<hipEvent_t, int64_t>> progress;
+  std::vector<hipEvent_t> event_pool;
+  bool dirty = false;
+  bool autotune = true, tuned = false;
+  int block = 256, grid = 0;
+  int graph_steps = 64;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int g_block = 0, g_grid = 0, g_steps = 0;
+};
+
+namespace {
+
+hipEvent_t take_event(ka_batch *b)
+{
+  if (!b->event_pool.empty()) {
+    hipEvent_t e = b->event_pool.back();
+    b->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  return e;
+}
+
+int full_grid(const ka_batch *b, int block)
+{
+  // step kernels hold up to 16 waves per CU
+  return b->cus * std::max(1, 16 / (block / 64));
+}
+
+hipError_t upload(ka_batch *b)
+{
+  hipError_t e = hipMemcpyAsync(b->d_tab, b->host_tab, sizeof(ka::BatchMember) * (size_t)std::max(1, b->n_members),
+                                hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess) e = ka::launch_batch_prepare(b->d_ctl, b->d_tab, b->n_members, b->block, b->stream);
+  if (e == hipSuccess) b->dirty = false;
+  return e;
+}
+
+void drop_graph(ka_batch *b)
+{
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->gexec = nullptr;
+  b->graph = nullptr;
+  b->g_steps = 0;
+}
+
+hipError_t ensure_graph(ka_batch *b)
+{
+  if (b->gexec && b->g_block == b->block && b->g_grid == b->grid && b->g_steps == b->graph_steps) return hipSuccess;
+  drop_graph(b);
+  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return e;
+  hipError_t le = hipSuccess;
+  for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k)
+    le = ka::launch_batch_step(b->d_ctl, b->d_tab, b->block, b->grid, b->stream);
+  e = hipStreamEndCapture(b->stream, &b->graph);
+  if (le != hipSuccess) e = le;
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    drop_graph(b);
+    return e;
+  }
+  b->g_block = b->block;
+  b->g_grid = b->grid;
+  b->g_steps = b->graph_steps;
+  return hipSuccess;
+}
+
+hipError_t enqueue_steps(ka_batch *b, int64_t n)
+{
+  hipError_t e = hipSuccess;
+  if (b->dirty) e = upload(b);
+  if (e != hipSuccess) return e;
+  int64_t left = n;
+  if (b->graph_steps > 0 && left >= b->graph_steps) {
+    e = ensure_graph(b);
+    while (e == hipSuccess && left >= b->graph_steps) {
+      e = hipGraphLaunch(b->gexec, b->stream);
+      left -= b->graph_steps;
+    }
+  }
+  while (e == hipSuccess && left > 0) {
+    e = ka::launch_batch_step(b->d_ctl, b->d_tab, b->block, b->grid, b->stream);
+    --left;
+  }
+  if (e != hipSuccess) return e;
+  b->step += n;
+  hipEvent_t ev = take_event(b);
+  e = hipEventRecord(ev, b->stream);
+  if (e != hipSuccess) return e;
+  b->progress.emplace_back(ev, b->step);
+  return hipSuccess;
+}
+
+int64_t max_classes(const ka_batch *b)
+{
+  int64_t c = 1;
+  for (int k = 0; k < b->n_members; ++k)
+    if (b->sims[k] && b->host_tab[k].s_end > b->step) c = std::max<int64_t>(c, b->host_tab[k].C);
+  return c;
+}
+
+// Time equal numbers of real steps under each candidate launch shape and keep the fastest.
+// The steps are the batch's own work: results do not depend on the launch shape.
+hipError_t autotune(ka_batch *b, int64_t &n_steps)
+{
+  const int blocks[3] = {128, 256, 512};
+  struct Cand { int block, grid; float ms; };
+  std::vector<Cand> cands;
+  for (int bl : blocks) {
+    const int fg = full_grid(b, bl);
+    for (int mul2 : {1, 2, 4}) cands.push_back({bl, fg * mul2 / 2, 0.f});
+  }
+  const int64_t probe = std::min<int64_t>(2 * max_classes(b), n_steps / (int64_t)(cands.size() + 1));
+  if (probe < 4) return hipSuccess;  // too little work to tune on; keep the default shape
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
+  for (auto &c : cands) {
+    if (c.block != b->block) {
+      b->block = c.block;
+      b->dirty = true;
+    }
+    b->grid = c.grid;
+    hipError_t e = hipSuccess;
+    if (b->dirty) e = upload(b);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
+    for (int64_t q = 0; q < probe && e == hipSuccess; ++q)
+      e = ka::launch_batch_step(b->d_ctl, b->d_tab, b->block, b->grid, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e != hipSuccess) return e;
+    evs.emplace_back(e0, e1);
+    b->step += probe;
+    n_steps -= probe;
+  }
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return e;
+  size_t best = 0;
+  for (size_t q = 0; q < cands.size(); ++q) {
+    (void)hipEventElapsedTime(&cands[q].ms, evs[q].first, evs[q].second);
+    (void)hipEventDestroy(evs[q].first);
+    (void)hipEventDestroy(evs[q].second);
+    if (cands[q].ms < cands[best].ms) best = q;
+  }
+  b->done_step = b->step;
+  if (b->block != cands[best].block) b->dirty = true;
+  b->block = cands[best].block;
+  b->grid = cands[best].grid;
+  b->tuned = true;
+  return hipSuccess;
+}
+
+void detach(ka_batch *b, int slot)
+{
+  ka_sim *s = b->sims[(size_t)slot];
+  s->t += b->sweeps[(size_t)slot];
+  s->batch = nullptr;
+  b->sims[(size_t)slot] = nullptr;
+  b->sweeps[(size_t)slot] = 0;
+  // the slot's device entry is already inactive for every later step; leave it in place
+}
+
+void harvest(ka_batch *b)
+{
+  while (!b->progress.empty()) {
+    hipError_t q = hipEventQuery(b->progress.front().first);
+    if (q != hipSuccess) break;
+    b->done_step = std::max(b->done_step, b->progress.front().second);
+    b->event_pool.push_back(b->progress.front().first);
+    b->progress.pop_front();
+  }
+}
+
+}  // namespace
+
+extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
+{
+  if (!out) return bfail(KA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (capacity < 1 || capacity > ka::kBatchMaxMembers)
+    return bfail(KA_EINVAL, "capacity must be in [1, %d]", ka::kBatchMaxMembers);
+  ka_batch *b = new (std::nothrow) ka_batch;
+  if (!b) return bfail(KA_ENOMEM, "host allocation failed");
+  (void)hipGetDevice(&b->device);
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
+    b->cus = cus;
+  b->capacity = capacity;
+  b->sims.assign((size_t)capacity, nullptr);
+  b->sweeps.assign((size_t)capacity, 0);
+  hipError_t e = hipSuccess;
+  if (hip_stream) {
+    b->stream = (hipStream_t)hip_stream;
+  } else {
+    e = hipStreamCreate(&b->stream);
+    b->own_stream = e == hipSuccess;
+  }
+  if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_tab, sizeof(ka::BatchMember) * (size_t)capacity, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_tab, sizeof(ka::BatchMember) * (size_t)capacity);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_ctl, sizeof(ka::BatchCtl));
+  if (e == hipSuccess) {
+    std::memset(b->host_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity);
+    e = hipMemsetAsync(b->d_ctl, 0, sizeof(ka::BatchCtl), b->stream);
+  }
+  if (e == hipSuccess) e = hipMemsetAsync(b->d_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity, b->stream);
+  if (e != hipSuccess) {
+    if (b->host_tab) (void)hipHostFree(b->host_tab);
+    (void)hipFree(b->d_tab);
+    (void)hipFree(b->d_ctl);
+    if (b->own_stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return bhip(e, "ka_batch_create");
+  }
+  b->grid = full_grid(b, b->block);
+  b->dirty = true;
+  *out = b;
+  return KA_OK;
+}
+
+extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
+{
+  if (!b || !s) return bfail(KA_EINVAL, "NULL argument");
+  if (s->batch) return bfail(KA_ESTATE, "sim is already a batch member");
+  if (!s->n) return bfail(KA_ESTATE, "sim has no device state");
+  if (s->device != b->device) return bfail(KA_EINVAL, "sim and batch are on different devices");
+  if (n_sweeps < 0) return bfail(KA_EINVAL, "n_sweeps < 0");
+  if (s->t + n_sweeps >= (1ll << 32)) return bfail(KA_ESTATE, "sweep index would reach 2^32");
+  int k = 0;
+  while (k < b->capacity && b->sims[(size_t)k]) ++k;
+  if (k == b->capacity) return bfail(KA_ESTATE, "batch is full (%d members)", b->capacity);
+  Guard dg(b->device);
+  // order the member's own earlier work (init, sweeps) before the batch's steps
+  if (s->stream != b->stream) {
+    hipEvent_t ev = take_event(b);
+    hipError_t e = hipEventRecord(ev, s->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+    b->event_pool.push_back(ev);
+    if (e != hipSuccess) return bhip(e, "ka_batch_add ordering");
+  }
+  ka::BatchMember m{};
+  m.n = s->n;
+  m.f = s->f;
+  m.adj = s->adj;
+  m.edges = s->edges;
+  m.class_start = s->class_start_d;
+  m.kind = s->lattice ? 0 : 1;
+  m.d = s->geom.d;
+  m.L = s->geom.L;
+  m.Q = s->geom.Q;
+  m.P = s->geom.P;
+  m.N = (int)s->N;
+  m.z = s->z;
+  m.m = s->m;
+  m.C = s->C;
+  m.planes = s->planes;
+  m.wpt = s->wpt;
+  m.key0 = (uint32_t)s->seed;
+  m.key1 = (uint32_t)(s->seed >> 32);
+  m.t0 = (uint32_t)s->t;
+  m.s_begin = b->step;
+  m.s_end = b->step + (int64_t)s->C * n_sweeps;
+  b->host_tab[k] = m;
+  b->sims[(size_t)k] = s;
+  b->sweeps[(size_t)k] = n_sweeps;
+  b->n_members = std::max(b->n_members, k + 1);
+  b->dirty = true;
+  s->batch = b;
+  if (slot) *slot = k;
+  return KA_OK;
+}
+
+extern "C" int ka_batch_run(ka_batch *b, int64_t n_steps)
+{
+  if (!b) return bfail(KA_EINVAL, "batch is NULL");
+  if (n_steps <= 0) return KA_OK;
+  Guard dg(b->device);
+  hipError_t e = hipSuccess;
+  if (b->dirty) e = upload(b);
+  if (e == hipSuccess && b->autotune && !b->tuned) e = autotune(b, n_steps);
+  if (e == hipSuccess && n_steps > 0) e = enqueue_steps(b, n_steps);
+  if (e != hipSuccess) return bhip(e, "ka_batch_run");
+  return KA_OK;
+}
+
+extern "C" int ka_batch_steps_left(const ka_batch *b, int64_t *steps_left)
+{
+  if (!b || !steps_left) return bfail(KA_EINVAL, "NULL argument");
+  int64_t left = 0;
+  for (int k = 0; k < b->n_members; ++k)
+    if (b->sims[(size_t)k]) left = std::max<int64_t>(left, b->host_tab[k].s_end - b->step);
+  *steps_left = left;
+  return KA_OK;
+}
+
+extern "C" int ka_batch_poll(ka_batch *b, int *slots, int max_slots, int *n_done)
+{
+  if (!b) return bfail(KA_EINVAL, "batch is NULL");
+  Guard dg(b->device);
+  harvest(b);
+  int got = 0;
+  for (int k = 0; k < b->n_members; ++k) {
+    if (!b->sims[(size_t)k] || b->host_tab[k].s_end > b->done_step) continue;
+    if (slots && got >= max_slots) break;
+    detach(b, k);
+    if (slots) slots[got] = k;
+    ++got;
+  }
+  if (n_done) *n_done = got;
+  return KA_OK;
+}
+
+extern "C" int ka_batch_wait_all(ka_batch *b)
+{
+  if (!b) return bfail(KA_EINVAL, "batch is NULL");
+  int64_t left = 0;
+  ka_batch_steps_left(b, &left);
+  int rc = ka_batch_run(b, left);
+  if (rc) return rc;
+  Guard dg(b->device);
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bhip(e, "ka_batch_wait_all");
+  harvest(b);
+  b->done_step = b->step;
+  for (int k = 0; k < b->n_members; ++k)
+    if (b->sims[(size_t)k]) detach(b, k);
+  return KA_OK;
+}
+
+extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
+{
+  if (!b) return bfail(KA_EINVAL, "batch is NULL");
+  switch (option) {
+    case KA_BOPT_AUTOTUNE:
+      b->autotune = value != 0;
+      return KA_OK;
+    case KA_BOPT_BLOCK:
+      if (value != 128 && value != 256 && value != 512) return bfail(KA_EINVAL, "block must be 128, 256 or 512");
+      if (b->block != (int)value) b->dirty = true;
+      b->block = (int)value;
+      b->autotune = false;
+      return KA_OK;
+    case KA_BOPT_GRID:
+      if (value < 1 || value > (1 << 20)) return bfail(KA_EINVAL, "grid out of range");
+      b->grid = (int)value;
+      b->autotune = false;
+      return KA_OK;
+    case KA_BOPT_GRAPH_STEPS:
+      if (value < 0 || value > 4096) return bfail(KA_EINVAL, "graph steps must be in [0, 4096]");
+      b->graph_steps = (int)value;
+      return KA_OK;
+    default:
+      return bfail(KA_EINVAL, "unknown batch option %d", option);
+  }
+}
+
+extern "C" int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *grid)
+{
+  if (!b) return bfail(KA_EINVAL, "batch is NULL");
+  int active = 0;
+  for (int k = 0; k < b->n_members; ++k) active += b->sims[(size_t)k] != nullptr;
+  if (step) *step = b->step;
+  if (members) *members = active;
+  if (block) *block = b->block;
+  if (grid) *grid = b->grid;
+  return KA_OK;
+}
+
+extern "C" void ka_batch_free(ka_batch *b)
+{
+  if (!b) return;
+  (void)ka_batch_wait_all(b);
+  Guard dg(b->device);
+  (void)hipStreamSynchronize(b->stream);
+  drop_graph(b);
+  for (auto &pr : b->progress) (void)hipEventDestroy(pr.first);
+  for (hipEvent_t ev : b->event_pool) (void)hipEventDestroy(ev);
+  (void)hipHostFree(b->host_tab);
+  (void)hipFree(b->d_tab);
+  (void)hipFree(b->d_ctl);
+  if (b->own_stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+// Called by ka_free for a sim that is still a batch member.
+int ka_batch_release_member(ka_batch *b, ka_sim *s)
+{
+  (void)s;
+  return ka_batch_wait_all(b);
+}

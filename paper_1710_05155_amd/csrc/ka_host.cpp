@@ -23,6 +23,12 @@ namespace {
 
 thread_local std::string g_err;
 
+}  // namespace
+
+void ka_set_error(const char *msg) { g_err = msg; }
+
+namespace {
+
 int fail(int code, const char *fmt, ...)
 {
   char buf[512];
@@ -602,6 +608,7 @@ int check_sim(const ka_sim *s)
 {
   if (!s) return fail(KA_EINVAL, "sim is NULL");
   if (!s->n) return fail(KA_ESTATE, "sim has no device state");
+  if (s->batch) return fail(KA_ESTATE, "sim is a batch member until its batch work is detached");
   return KA_OK;
 }
 
@@ -900,6 +907,7 @@ extern "C" int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t
 extern "C" int ka_set_option(ka_sim *s, int option, int64_t value)
 {
   if (!s) return fail(KA_EINVAL, "sim is NULL");
+  if (s->batch) return fail(KA_ESTATE, "sim is a batch member");
   if (option == KA_OPT_PATH) {
     if (value < 0 || value > 2) return fail(KA_EINVAL, "path must be 0, 1 or 2");
     if (value == 2 && !s->lds_fits) return fail(KA_EINVAL, "instance does not fit in LDS");
@@ -937,6 +945,7 @@ extern "C" int ka_sim_path(const ka_sim *s, int *path)
 extern "C" void ka_free(ka_sim *s)
 {
   if (!s) return;
+  if (s->batch) (void)ka_batch_release_member(s->batch, s);
   DeviceGuard dg(s->device);
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   harvest_timing(s);

@@ -149,7 +149,8 @@ struct BatchCtl {
   int prefix[kBatchMaxMembers + 1];   // tile prefix over members for `step`
 };
 
-hipError_t launch_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int block, hipStream_t s);
+hipError_t launch_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int n_members, int block,
+                                hipStream_t s);
 hipError_t launch_batch_step(BatchCtl *ctl, const BatchMember *mem, int block, int grid, hipStream_t s);
 
 }  // namespace ka

@@ -63,3 +63,9 @@ struct ka_sim {
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
   std::vector<hipEvent_t> event_pool;
 };
+
+// Error message of the calling thread (ka_last_error), shared by the host sources.
+void ka_set_error(const char *msg);
+// Finish the batch work of a member that is being freed.
+int ka_batch_release_member(ka_batch *b, ka_sim *s);
+

@@ -27,7 +27,13 @@ SYMBOLS = (
     "ka_graph_export", "ka_graph_free", "ka_footprint", "ka_init", "ka_init_k", "ka_sweep",
     "ka_observe", "ka_run", "ka_get_state", "ka_set_state", "ka_sim_info", "ka_set_option",
     "ka_timing", "ka_sim_path", "ka_free", "ka_last_error",
+    "ka_batch_create", "ka_batch_add", "ka_batch_run", "ka_batch_steps_left", "ka_batch_poll",
+    "ka_batch_wait_all", "ka_batch_set_option", "ka_batch_info", "ka_batch_free",
 )
+KA_BOPT_AUTOTUNE = 1
+KA_BOPT_BLOCK = 2
+KA_BOPT_GRID = 3
+KA_BOPT_GRAPH_STEPS = 4
 
 
 class KaError(RuntimeError):
@@ -74,6 +80,15 @@ def load():
         "ka_sim_path": ([P, P], I),
         "ka_free": ([P], None),
         "ka_last_error": ([], ctypes.c_char_p),
+        "ka_batch_create": ([I, P, PP], I),
+        "ka_batch_add": ([P, P, I64, P], I),
+        "ka_batch_run": ([P, I64], I),
+        "ka_batch_steps_left": ([P, P], I),
+        "ka_batch_poll": ([P, P, I, P], I),
+        "ka_batch_wait_all": ([P], I),
+        "ka_batch_set_option": ([P, I, I64], I),
+        "ka_batch_info": ([P, P, P, P, P], I),
+        "ka_batch_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -282,6 +297,87 @@ def ka_free(s: Sim) -> None:
 def ka_last_error() -> str:
     msg = load().ka_last_error()
     return msg.decode() if msg else ""
+
+
+# ------------------------------------------------------------------------------ batches
+class Batch:
+    """Owning handle of a ka_batch.  Members are Sim objects; the batch keeps them alive."""
+
+    def __init__(self, handle, stream):
+        self._h = handle
+        self.stream = stream
+        self.members = {}
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h and _lib is not None:
+            _lib.ka_batch_free(self._h)
+        self._h = None
+        self.members = {}
+
+    def __del__(self):
+        self.free()
+
+
+def ka_batch_create(capacity: int, stream=None) -> Batch:
+    h = ctypes.c_void_p()
+    _check(load().ka_batch_create(int(capacity), _stream_handle(stream), ctypes.byref(h)))
+    return Batch(h, stream)
+
+
+def ka_batch_add(b: Batch, s: Sim, n_sweeps: int) -> int:
+    slot = ctypes.c_int()
+    _check(load().ka_batch_add(b.handle, s.handle, int(n_sweeps), ctypes.byref(slot)))
+    b.members[slot.value] = s
+    return slot.value
+
+
+def ka_batch_run(b: Batch, n_steps: int) -> None:
+    _check(load().ka_batch_run(b.handle, int(n_steps)))
+
+
+def ka_batch_steps_left(b: Batch) -> int:
+    v = ctypes.c_int64()
+    _check(load().ka_batch_steps_left(b.handle, ctypes.byref(v)))
+    return v.value
+
+
+def ka_batch_poll(b: Batch) -> list:
+    """Slots whose members finished on the device (now detached)."""
+    cap = max(1, len(b.members))
+    slots = np.empty(cap, dtype=np.int32)
+    n = ctypes.c_int()
+    _check(load().ka_batch_poll(b.handle, _ptr(slots), cap, ctypes.byref(n)))
+    out = [int(x) for x in slots[: n.value]]
+    for k in out:
+        b.members.pop(k, None)
+    return out
+
+
+def ka_batch_wait_all(b: Batch) -> None:
+    _check(load().ka_batch_wait_all(b.handle))
+    b.members = {}
+
+
+def ka_batch_set_option(b: Batch, option: int, value: int) -> None:
+    _check(load().ka_batch_set_option(b.handle, option, int(value)))
+
+
+def ka_batch_info(b: Batch):
+    step = ctypes.c_int64()
+    members = ctypes.c_int()
+    block = ctypes.c_int()
+    grid = ctypes.c_int()
+    _check(load().ka_batch_info(b.handle, ctypes.byref(step), ctypes.byref(members), ctypes.byref(block),
+                                ctypes.byref(grid)))
+    return step.value, members.value, block.value, grid.value
+
+
+def ka_batch_free(b: Batch) -> None:
+    b.free()
 
 
 # ------------------------------------------------------------------------------ host helpers

@@ -1,0 +1,182 @@
+"""Batched execution: every member of a batch ends in exactly the state it reaches alone.
+
+Members mix 2D/3D lattices and random regular graphs of degree 3..6, one to five words
+per site, different m, densities, seeds and sweep counts (so they finish at different
+steps).  The reference for each member is the same sim advanced alone with ka_sweep (itself
+parity-tested against the oracle); a few members are also checked against the oracle
+directly.  Launch shapes (workgroup size, persistent grid, graph capture, autotuning) must
+not change any bit, and members added while the batch runs must also match.
+"""
+import numpy as np
+import pytest
+
+from paper_1710_05155_amd import ka
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+MEMBERS = [
+    # kind, size, z, m, rho, R, seed, sweeps
+    ("lat", (2, 8), 4, 2, 0.6, 64, 1, 5),
+    ("lat", (2, 12), 4, 1, 0.5, 128, 2, 9),
+    ("lat", (2, 64), 4, 2, 0.7, 64, 3, 4),
+    ("lat", (3, 8), 6, 3, 0.8, 256, 4, 3),
+    ("lat", (3, 12), 6, 2, 0.65, 64, 5, 6),
+    ("lat", (2, 32), 4, 3, 0.85, 192, 6, 2),
+    ("rrg", 64, 3, 1, 0.5, 64, 7, 7),
+    ("rrg", 300, 6, 3, 0.8, 128, 8, 3),
+    ("rrg", 2000, 4, 2, 0.65, 64, 9, 5),
+    ("rrg", 500, 5, 3, 0.7, 192, 10, 4),
+    ("rrg", 1000, 3, 0, 0.55, 320, 11, 2),
+    ("lat", (3, 16), 6, 3, 0.88, 128, 12, 1),
+]
+
+
+def _graph(spec):
+    kind, size, z = spec[0], spec[1], spec[2]
+    if kind == "lat":
+        return ka.ka_graph_lattice(*size)
+    return ka.ka_graph_rrg(size, z, 31 + size)
+
+
+def _make(spec, g, stream=None):
+    _, _, _, m, rho, R, seed, _ = spec
+    return ka.ka_init(g, m, rho, seed, R, stream=stream)
+
+
+def _solo_states(graphs):
+    out = []
+    for spec, g in zip(MEMBERS, graphs):
+        s = _make(spec, g)
+        ka.ka_sweep(s, spec[7])
+        out.append(ka.ka_get_state(s))
+        s.free()
+    return out
+
+
+def _run_batch(graphs, options=()):
+    b = ka.ka_batch_create(64)
+    for opt, val in options:
+        ka.ka_batch_set_option(b, opt, val)
+    sims = []
+    for spec, g in zip(MEMBERS, graphs):
+        s = _make(spec, g)
+        ka.ka_batch_add(b, s, spec[7])
+        sims.append(s)
+    ka.ka_batch_wait_all(b)
+    states = [ka.ka_get_state(s) for s in sims]
+    info = ka.ka_batch_info(b)
+    b.free()
+    return states, info
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    return [_graph(spec) for spec in MEMBERS]
+
+
+@pytest.fixture(scope="module")
+def solo(graphs):
+    _say("batch: solo references")
+    return _solo_states(graphs)
+
+
+def _assert_same(states, solo):
+    for k, (a, b) in enumerate(zip(states, solo)):
+        for x, y in zip(a, b):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), f"member {k} ({MEMBERS[k][:2]})"
+
+
+@pytest.mark.parametrize("options", [
+    (),                                                                         # autotuned, graphs
+    ((ka.KA_BOPT_BLOCK, 128), (ka.KA_BOPT_GRID, 7), (ka.KA_BOPT_GRAPH_STEPS, 0)),
+    ((ka.KA_BOPT_BLOCK, 512), (ka.KA_BOPT_GRID, 3000), (ka.KA_BOPT_GRAPH_STEPS, 5)),
+    ((ka.KA_BOPT_BLOCK, 256), (ka.KA_BOPT_GRID, 1), (ka.KA_BOPT_GRAPH_STEPS, 64)),
+])
+def test_batch_members_equal_solo(graphs, solo, options):
+    _say(f"batch options {options}")
+    states, info = _run_batch(graphs, options)
+    _assert_same(states, solo)
+    assert info[1] == 0  # all members detached
+
+
+def test_batch_members_match_oracle(oracle):
+    """Two members checked against the oracle directly (all replicas, state and counts)."""
+    g2 = ka.ka_graph_lattice(2, 12)
+    og2 = oracle.lattice(2, 12)
+    gr = ka.ka_graph_rrg(300, 4, 5)
+    ogr = oracle.graph_from_adjacency(oracle.rrg_adjacency(300, 4, 5)[0])
+    _say("batch vs oracle")
+    b = ka.ka_batch_create(4)
+    a = ka.ka_init(g2, 2, 0.6, 21, 128)
+    c = ka.ka_init(gr, 1, 0.55, 22, 64)
+    ka.ka_batch_add(b, a, 6)
+    ka.ka_batch_add(b, c, 9)
+    ka.ka_batch_wait_all(b)
+    for sim, og, m, rho, seed, R, n in [(a, og2, 2, 0.6, 21, 128, 6), (c, ogr, 1, 0.55, 22, 64, 9)]:
+        orc = oracle.Sim(og, m, oracle.k_from_rho(og.N, rho), seed, range(R))
+        orc.sweep(n)
+        n_, n0_, f_, t_ = ka.ka_get_state(sim)
+        assert t_ == n
+        assert np.array_equal(n_, oracle.pack(orc.occ)) and np.array_equal(f_, oracle.pack(orc.moved))
+        t, dens, ov, pers = ka.ka_observe(sim)
+        od, oo, op = orc.observe()
+        assert np.array_equal(dens, od) and np.array_equal(ov, oo) and np.array_equal(pers, op)
+
+
+def test_members_added_while_running(graphs, solo):
+    """Continuous batching: members join after the batch has started and leave as they
+    finish; each still ends in its solo state."""
+    _say("batch: staggered admission")
+    b = ka.ka_batch_create(8)  # fewer slots than members: slots are reused
+    ka.ka_batch_set_option(b, ka.KA_BOPT_GRAPH_STEPS, 4)
+    pending = list(range(len(MEMBERS)))
+    sims = {}
+    results = {}
+    rounds = 0
+    while pending or b.members:
+        while pending and len(b.members) < 8:
+            k = pending.pop(0)
+            s = _make(MEMBERS[k], graphs[k])
+            slot = ka.ka_batch_add(b, s, MEMBERS[k][7])
+            sims[slot] = (k, s)
+        ka.ka_batch_run(b, 3)
+        for slot in ka.ka_batch_poll(b):
+            k, s = sims.pop(slot)
+            results[k] = ka.ka_get_state(s)
+            s.free()
+        rounds += 1
+        assert rounds < 10_000
+        if not pending and b.members and ka.ka_batch_steps_left(b) == 0:
+            ka.ka_batch_wait_all(b)
+            for slot, (k, s) in list(sims.items()):
+                results[k] = ka.ka_get_state(s)
+            sims.clear()
+    b.free()
+    assert sorted(results) == list(range(len(MEMBERS)))
+    _assert_same([results[k] for k in range(len(MEMBERS))], solo)
+
+
+def test_batch_errors(graphs):
+    b = ka.ka_batch_create(1)
+    s = _make(MEMBERS[0], graphs[0])
+    ka.ka_batch_add(b, s, 2)
+    with pytest.raises(ka.KaError) as e:
+        ka.ka_sweep(s, 1)
+    assert e.value.code == ka.KA_ESTATE
+    s2 = _make(MEMBERS[1], graphs[1])
+    with pytest.raises(ka.KaError) as e:
+        ka.ka_batch_add(b, s2, 1)          # full
+    assert e.value.code == ka.KA_ESTATE
+    b2 = ka.ka_batch_create(2)
+    with pytest.raises(ka.KaError):
+        ka.ka_batch_add(b2, s, 1)          # already a member elsewhere
+    ka.ka_batch_wait_all(b)
+    assert s.t == 2
+    ka.ka_sweep(s, 1)                      # detached: usable again
+    b.free()
+    b2.free()
