@@ -79,10 +79,10 @@ def measured_traffic(kernel_sources, counters_file):
 
 
 def obs_grid(w):
-    from paper_1710_05155_amd import ka
+    from paper_1710_05155_amd import workloads
     if "obs_every" in w:
         return list(range(0, w["sweeps"] + 1, w["obs_every"]))
-    return ka.log_time_grid(w["sweeps"])
+    return workloads.log_time_grid(w["sweeps"])
 
 
 def cpu_baseline(w, seconds_target=15.0):
@@ -111,12 +111,142 @@ def cpu_baseline(w, seconds_target=15.0):
                       f"(one replica per thread), sweeps only"}
 
 
+def graph_bytes_model(adj, eu, ev, ec, C, z, W):
+    """Algorithmic bytes of one sweep over a general graph, summed over its class passes:
+    per class, the distinct sites read (endpoints and their neighbours, at most N) x 8 B per
+    word, the class records (16 B per edge), the two adjacency rows per edge (4z B each),
+    the endpoint words written (2 x 8 B per edge and word) and their moved-ever words read
+    and written (2 x 16 B per edge and word)."""
+    import numpy as np
+    N = adj.shape[0]
+    total = 0
+    for c in range(C):
+        sel = ec == c
+        Ec = int(sel.sum())
+        touched = np.zeros(N, dtype=bool)
+        touched[eu[sel]] = True
+        touched[ev[sel]] = True
+        touched[adj[eu[sel]].ravel()] = True
+        touched[adj[ev[sel]].ravel()] = True
+        total += int(touched.sum()) * 8 * W + Ec * (16 + 2 * 4 * z + 2 * 8 * W + 2 * 16 * W)
+    return total
+
+
+def run_batch_workload(args):
+    """256 uneven instances advanced together by the batched step kernel, against the same
+    jobs run one at a time with the single-instance path."""
+    import numpy as np
+    import torch
+    from paper_1710_05155_amd import ka, workloads
+
+    sweeps = args.sweeps or 1000
+    man = workloads.batch_manifest(256, sweeps=sweeps)
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    graphs, bytes_per_sweep = {}, {}
+    for inst in man:
+        key = (inst["kind"], inst.get("d"), inst.get("L"), inst.get("N"), inst.get("z"), inst.get("graph_seed"))
+        inst["key"] = key
+        if key in graphs:
+            continue
+        if inst["kind"] == "lattice":
+            graphs[key] = ka.ka_graph_lattice(inst["d"], inst["L"])
+            bytes_per_sweep[key] = 20 * inst["N"] * (inst["R"] // 64) * 4 * inst["d"]
+        else:
+            g = ka.ka_graph_rrg(inst["N"], inst["z"], inst["graph_seed"])
+            graphs[key] = g
+            adj, eu, ev, ec = ka.ka_graph_export(g)
+            bytes_per_sweep[key] = graph_bytes_model(adj, eu, ev, ec, g.C, g.z, inst["R"] // 64)
+    log(f"built {len(graphs)} graphs in {time.perf_counter() - t0:.1f} s")
+    attempts = sum(graphs[i["key"]].N * i["R"] * i["sweeps"] for i in man)
+    model_bytes = sum(bytes_per_sweep[i["key"]] * i["sweeps"] for i in man)
+
+    shape = {}
+
+    def batched(timed_kernel):
+        sims = [ka.ka_init(graphs[i["key"]], i["m"], i["rho"], i["seed"], i["R"], stream=stream) for i in man]
+        b = ka.ka_batch_create(len(sims), stream=stream)
+        if shape:
+            ka.ka_batch_set_option(b, ka.KA_BOPT_BLOCK, shape["block"])
+        for s, i in zip(sims, man):
+            ka.ka_batch_add(b, s, i["sweeps"])
+        steps = ka.ka_batch_steps_left(b)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ka.ka_batch_run(b, steps)
+        e1.record(stream)
+        _, _, block, _ = ka.ka_batch_info(b)
+        ka.ka_batch_wait_all(b)
+        for s in sims:
+            _, dens, _, _ = ka.ka_observe(s)
+            assert (dens == s.K).all(), "particle number not conserved"
+        b.free()
+        for s in sims:
+            s.free()
+        shape.update(block=block)
+        if timed_kernel is not None:
+            timed_kernel.append((e0.elapsed_time(e1), steps))
+        return steps
+
+    def serial():
+        for i in man:
+            s = ka.ka_init(graphs[i["key"]], i["m"], i["rho"], i["seed"], i["R"], stream=stream)
+            ka.ka_sweep(s, i["sweeps"])
+            _, dens, _, _ = ka.ka_observe(s)
+            assert (dens == s.K).all()
+            s.free()
+
+    for k in range(args.warmup):
+        t = time.perf_counter()
+        batched(None)
+        log(f"warmup {k}: {time.perf_counter() - t:.2f} s, tuned shape {shape}")
+    kern = []
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for k in range(args.steps):
+        steps = batched(kern)
+        log(f"step {k}: step kernels {steps}, {kern[-1][0]:.1f} ms of them")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    result = {
+        "metric": "site-replica move attempts/s (1 GPU)",
+        "value": attempts * args.steps / wall,
+        "unit": "site-replica move attempts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall * 1000.0 / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "256 uneven instances (2D L 32-512, 3D L 16-128, RRG N 2^12-2^18 z 3-5, "
+                               f"m 1..z-1, rho U[0.5,0.9], 64 replicas), {sweeps} sweeps each, batched "
+                               "step kernel in captured graphs, autotuned launch shape",
+                   "instances": len(man), "sites_total": int(sum(graphs[i["key"]].N for i in man)),
+                   "launch_shape": shape},
+    }
+    ms = sum(k[0] for k in kern)
+    launches = sum(k[1] for k in kern)
+    achieved = model_bytes * args.steps / (ms / 1000.0) / 1e9
+    result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch_step",
+                          "avg_launch_us": ms * 1000.0 / launches, "bytes_per_launch": model_bytes / (launches / args.steps)}
+    if not args.no_serial:
+        log("serial one-at-a-time baseline ...")
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        serial()
+        torch.cuda.synchronize()
+        ws = time.perf_counter() - t
+        result["serial_one_at_a_time"] = {"value": attempts / ws, "ms": ws * 1000.0}
+        result["speedup_vs_serial"] = ws / (wall / args.steps)
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="cubic128", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="cubic128", choices=sorted(WORKLOADS) + ["batch256"])
     ap.add_argument("--timing-every", type=int, default=64,
                     help="bracket every k-th class-pass launch with HIP events")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -125,12 +255,18 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that a "
                          "hardware-counter run can scale HBM byte counters by a kernel of known traffic")
+    ap.add_argument("--no-serial", action="store_true", help="batch workload: skip the one-at-a-time baseline")
+    ap.add_argument("--replicas", type=int, default=None, help="override the replica count (exploration only)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the replica planes of a job shard across GPUs "
               "with no communication, but multi-GPU runs are not part of it (use --gpus 1).",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch256":
+        run_batch_workload(args)
+        return
 
     import torch
     from paper_1710_05155_amd import ka
@@ -144,6 +280,8 @@ def main():
         g = ka.ka_graph_rrg(w["N"], w["z"], w["graph_seed"])
     if args.sweeps is not None:
         w = dict(w, sweeps=args.sweeps)
+    if args.replicas is not None:
+        w = dict(w, R=args.replicas, desc=w["desc"] + f" [replicas overridden: {args.replicas}]")
     N, R, sweeps = g.N, w["R"], w["sweeps"]
     if args.calibrate_copy_mib > 0:
         nbytes = args.calibrate_copy_mib << 20
@@ -223,7 +361,7 @@ def main():
         achieved = B / avg_s / 1e9
         csrc = os.path.join(ROOT, "paper_1710_05155_amd", "csrc")
         traffic = None
-        if args.workload == "cubic128":
+        if args.workload == "cubic128" and R == 256:
             traffic = measured_traffic([os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")],
                                        os.path.join(ROOT, "profiles", "k_pass_lattice_cubic128.counters.txt"))
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

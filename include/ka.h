@@ -169,9 +169,9 @@ int ka_batch_create(int capacity, void *hip_stream, ka_batch **out);
  * ka_batch_wait_all) every other call on it returns KA_ESTATE.  *slot receives its slot. */
 int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot);
 
-/* Enqueue n_steps step kernels (asynchronous).  The first call tunes the launch shape
- * (workgroup size and number of persistent workgroups) on its first steps unless
- * KA_BOPT_AUTOTUNE is 0. */
+/* Enqueue n_steps steps (asynchronous).  Each step is one kernel launch per words-per-
+ * thread variant present, one workgroup per tile of active work.  The first call tunes the
+ * tile (workgroup) size on its first steps unless KA_BOPT_AUTOTUNE is 0. */
 int ka_batch_run(ka_batch *b, int64_t n_steps);
 
 /* Steps still to enqueue until every member's work is enqueued. */
@@ -184,17 +184,17 @@ int ka_batch_poll(ka_batch *b, int *slots, int max_slots, int *n_done);
 /* Run every member to completion, wait, and detach all members. */
 int ka_batch_wait_all(ka_batch *b);
 
-/* Options: KA_BOPT_AUTOTUNE (1 default / 0), KA_BOPT_BLOCK (128, 256, 512; disables
- * autotuning), KA_BOPT_GRID (persistent workgroups; disables autotuning),
- * KA_BOPT_GRAPH_STEPS (step kernels per captured graph; 0 = plain launches). */
+/* Options: KA_BOPT_AUTOTUNE (1 default / 0), KA_BOPT_BLOCK (tile = workgroup size: 128,
+ * 256 or 512; disables autotuning), KA_BOPT_GRAPH_STEPS (steps per captured graph, default
+ * 64; 0 = plain launches). */
 #define KA_BOPT_AUTOTUNE 1
 #define KA_BOPT_BLOCK 2
-#define KA_BOPT_GRID 3
 #define KA_BOPT_GRAPH_STEPS 4
 int ka_batch_set_option(ka_batch *b, int option, int64_t value);
 
-/* Global step (enqueued), active members, and the launch shape in use. */
-int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *grid);
+/* Global step (enqueued), attached members, tile size in use, and tiles per step of the
+ * current segment (any may be NULL). */
+int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *tiles);
 
 /* Finish all members (as ka_batch_wait_all) and release the batch. */
 void ka_batch_free(ka_batch *b);

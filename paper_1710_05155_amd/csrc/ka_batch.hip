@@ -3,12 +3,14 @@
 // device code as the single-instance passes (ka_device.h), so a member's result does not
 // depend on what else is in the batch.
 //
-// Work list: every member contributes planes x ceil(threads of its current class / BLOCK)
-// tiles of BLOCK threads.  The tile prefix over members for the current step lives in
-// BatchCtl; each workgroup copies it to LDS and takes one contiguous range of tiles
-// (ranges ordered so that each XCD holds a contiguous part of the work).  The last
-// workgroup to finish advances the global step and builds the next step's prefix, so a
-// captured graph of identical launches replays any number of steps without host work.
+// Work list: between membership changes ("segments") every member owns a fixed number of
+// tiles of BLOCK threads per step: planes x tiles per plane, where a lattice class always
+// has the same size and a graph member is padded to its largest class (workgroups past the
+// current class exit at once).  The prepare kernel writes the tile -> (member, local tile)
+// table of a segment; each step kernel then runs one workgroup per tile, mapped so that
+// each XCD holds a contiguous range of tiles (stencil halos meet in its L2).  The step
+// index is a device base plus the launch's offset, so a captured graph of G step kernels
+// followed by one "base += G" kernel replays any number of steps.
 #include "ka_device.h"
 
 namespace ka {
@@ -33,61 +35,11 @@ __device__ __forceinline__ int class_sublattice(int D, int mu, int r, int q)
   return a[0] + 4 * a[1] + 16 * a[2];
 }
 
-template <int BLOCK>
-__device__ __forceinline__ int tiles_per_plane(const BatchMember &mb, int c)
-{
-  if (mb.kind == 0) {
-    const int nsub = mb.d == 2 ? 4 : 16;
-    const int threads = nsub * 64 * ((mb.P + 63) / 64);
-    return (threads + BLOCK - 1) / BLOCK;
-  }
-  const int count = mb.class_start[c + 1] - mb.class_start[c];
-  return (count + BLOCK - 1) / BLOCK;
-}
-
-template <int BLOCK>
-__device__ __forceinline__ int member_tiles(const BatchMember &mb, long long s)
-{
-  if (s < mb.s_begin || s >= mb.s_end) return 0;
-  const int c = (int)((s - mb.s_begin) % mb.C);
-  return mb.planes * tiles_per_plane<BLOCK>(mb, c);
-}
-
-// Block-wide exclusive prefix of member tiles at step s into out[0..n] (out[n] = total).
-template <int BLOCK>
-__device__ void build_prefix(const BatchMember *mem, int n, long long s, int *out, int *scratch)
-{
-  const int tid = (int)threadIdx.x;
-  // each thread sums a contiguous run of members, then a scan over thread totals
-  const int per = (n + BLOCK - 1) / BLOCK;
-  const int b0 = tid * per, b1 = min(n, b0 + per);
-  int local = 0;
-  for (int k = b0; k < b1; ++k) local += member_tiles<BLOCK>(mem[k], s);
-  scratch[tid] = local;
-  __syncthreads();
-  if (tid == 0) {
-    int acc = 0;
-    for (int q = 0; q < BLOCK; ++q) {
-      const int v = scratch[q];
-      scratch[q] = acc;
-      acc += v;
-    }
-    out[n] = acc;
-  }
-  __syncthreads();
-  int acc = scratch[tid];
-  for (int k = b0; k < b1; ++k) {
-    out[k] = acc;
-    acc += member_tiles<BLOCK>(mem[k], s);
-  }
-  __syncthreads();
-}
-
-template <int BLOCK>
+template <int BLOCK, int WPT>
 __device__ __forceinline__ void run_lattice_tile(const BatchMember &mb, int local, int c, uint32_t t)
 {
   const int nsub = mb.d == 2 ? 4 : 16;
-  const int bpp = tiles_per_plane<BLOCK>(mb, c);
+  const int bpp = mb.tiles_per_plane;
   const int plane = local / bpp;
   const int blk = local - plane * bpp;
   const int gid = blk * BLOCK + (int)threadIdx.x;
@@ -105,151 +57,121 @@ __device__ __forceinline__ void run_lattice_tile(const BatchMember &mb, int loca
   g.Q = mb.Q;
   g.P = mb.P;
   g.N = mb.N;
-  const size_t off = (size_t)plane * (size_t)mb.N * (size_t)mb.wpt;
+  const size_t off = (size_t)plane * (size_t)mb.N * WPT;
   u64 *n = mb.n + off, *f = mb.f + off;
   if (mb.d == 2) {
-    if (mb.wpt == 2) {
-      if (mu == 0) lattice_edge<2, 0, 2>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-      else lattice_edge<2, 1, 2>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-    } else {
-      if (mu == 0) lattice_edge<2, 0, 1>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-      else lattice_edge<2, 1, 1>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-    }
+    if (mu == 0) lattice_edge<2, 0, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
+    else lattice_edge<2, 1, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
   } else {
-    if (mb.wpt == 2) {
-      if (mu == 0) lattice_edge<3, 0, 2>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-      else if (mu == 1) lattice_edge<3, 1, 2>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-      else lattice_edge<3, 2, 2>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-    } else {
-      if (mu == 0) lattice_edge<3, 0, 1>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-      else if (mu == 1) lattice_edge<3, 1, 1>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-      else lattice_edge<3, 2, 1>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-    }
+    if (mu == 0) lattice_edge<3, 0, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
+    else if (mu == 1) lattice_edge<3, 1, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
+    else lattice_edge<3, 2, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
   }
 }
 
-template <int BLOCK>
+template <int BLOCK, int WPT>
 __device__ __forceinline__ void run_graph_tile(const BatchMember &mb, int local, int c, uint32_t t)
 {
-  const int b0 = mb.class_start[c];
-  const int count = mb.class_start[c + 1] - b0;
-  const int bpp = (count + BLOCK - 1) / BLOCK;
+  const int bpp = mb.tiles_per_plane;
   const int plane = local / bpp;
   const int blk = local - plane * bpp;
+  const int b0 = mb.class_start[c];
+  const int count = mb.class_start[c + 1] - b0;
   const int k = blk * BLOCK + (int)threadIdx.x;
   if (k >= count) return;
-  const size_t off = (size_t)plane * (size_t)mb.N * (size_t)mb.wpt;
+  const size_t off = (size_t)plane * (size_t)mb.N * WPT;
   u64 *n = mb.n + off, *f = mb.f + off;
   const int4 E = mb.edges[b0 + k];
-  switch (mb.z * 4 + mb.wpt) {
-    case 3 * 4 + 1: graph_edge<3, 1>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 3 * 4 + 2: graph_edge<3, 2>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 4 * 4 + 1: graph_edge<4, 1>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 4 * 4 + 2: graph_edge<4, 2>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 5 * 4 + 1: graph_edge<5, 1>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 5 * 4 + 2: graph_edge<5, 2>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 6 * 4 + 1: graph_edge<6, 1>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 6 * 4 + 2: graph_edge<6, 2>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
+  switch (mb.z) {
+    case 3: graph_edge<3, WPT>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
+    case 4: graph_edge<4, WPT>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
+    case 5: graph_edge<5, WPT>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
+    case 6: graph_edge<6, WPT>(n, f, mb.adj, E, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
     default: break;
   }
 }
 
-// After the member table changed: set the member count and rebuild the work list of the
-// step the next step kernel executes.  The tile size is BLOCK of the step kernels that
-// follow, so this kernel is launched with the same BLOCK.
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int n)
+// Tile table of the segment that starts at `step`: members with `wpt` words per thread
+// that are active at `step` own planes x tiles_per_plane consecutive tiles, in member
+// order.  One workgroup; the total is written to *total.
+__global__ __launch_bounds__(1024) void k_batch_prepare(const BatchMember *mem, int n, long long step, int wpt,
+                                                        BatchTiles tiles, int *total)
 {
-  __shared__ int scratch[BLOCK];
-  const long long s = ctl->step;
-  build_prefix<BLOCK>(mem, n, s, ctl->prefix, scratch);
-  if (threadIdx.x == 0) {
-    ctl->n_members = n;
-    ctl->done = 0;
+  __shared__ int start[kBatchMaxMembers + 1];
+  const int tid = (int)threadIdx.x;
+  if (tid == 0) {
+    int acc = 0;
+    for (int k = 0; k < n; ++k) {
+      start[k] = acc;
+      const BatchMember &mb = mem[k];
+      if (mb.wpt == wpt && step >= mb.s_begin && step < mb.s_end) acc += mb.planes * mb.tiles_per_plane;
+    }
+    start[n] = acc;
+    *total = acc;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const int a = start[k], b = start[k + 1];
+    for (int q = a + tid; q < b; q += (int)blockDim.x) {
+      tiles.member[q] = k;
+      tiles.local[q] = q - a;
+    }
   }
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_batch_step(BatchCtl *ctl, const BatchMember *mem)
+template <int BLOCK, int WPT>
+__global__ __launch_bounds__(BLOCK) void k_batch_step(const BatchMember *mem, BatchTiles tiles,
+                                                           const long long *base, int offset)
 {
-  __shared__ int sp[kBatchMaxMembers + 1];
-  __shared__ int scratch[BLOCK];
-  __shared__ long long s_step;
-  __shared__ int s_n;
-  __shared__ int s_last;
-  const int tid = (int)threadIdx.x;
-  if (tid == 0) {
-    s_step = ctl->step;
-    s_n = ctl->n_members;
-  }
-  __syncthreads();
-  const long long s = s_step;
-  const int n = s_n;
-  for (int k = tid; k <= n; k += BLOCK) sp[k] = ctl->prefix[k];
-  __syncthreads();
-  const int total = sp[n];
-  const int G = (int)gridDim.x;
-  const int lb = xcd_remap((int)blockIdx.x, G);
-  const int per = (total + G - 1) / G;
-  const int t_begin = lb * per;
-  const int t_end = min(total, t_begin + per);
-  for (int tile = t_begin; tile < t_end; ++tile) {
-    // member holding this tile: the last k with sp[k] <= tile (members with no tiles have
-    // sp[k] == sp[k+1] and are skipped by taking the last such k)
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (sp[mid] <= tile) lo = mid;
-      else hi = mid - 1;
-    }
-    const BatchMember mb = mem[lo];
-    const int local = tile - sp[lo];
-    const long long rel = s - mb.s_begin;
-    const int c = (int)(rel % mb.C);
-    const uint32_t t = mb.t0 + (uint32_t)(rel / mb.C);
-    if (mb.kind == 0) run_lattice_tile<BLOCK>(mb, local, c, t);
-    else run_graph_tile<BLOCK>(mb, local, c, t);
-  }
-  // the last workgroup to finish advances the step and prepares the next work list
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    const unsigned old = atomicAdd(&ctl->done, 1u);
-    s_last = (old == (unsigned)(G - 1));
-  }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    build_prefix<BLOCK>(mem, n, s + 1, ctl->prefix, scratch);
-    if (tid == 0) {
-      ctl->step = s + 1;
-      ctl->done = 0;
-    }
-  }
+  const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
+  const long long s = *base + offset;
+  const int k = tiles.member[tile];
+  const int local = tiles.local[tile];
+  const BatchMember mb = mem[k];
+  if (s < mb.s_begin || s >= mb.s_end) return;
+  const long long rel = s - mb.s_begin;
+  const int c = (int)(rel % mb.C);
+  const uint32_t t = mb.t0 + (uint32_t)(rel / mb.C);
+  if (mb.kind == 0) run_lattice_tile<BLOCK, WPT>(mb, local, c, t);
+  else run_graph_tile<BLOCK, WPT>(mb, local, c, t);
+}
+
+__global__ void k_batch_advance(long long *base, int by)
+{
+  if (threadIdx.x == 0 && blockIdx.x == 0) *base += by;
 }
 
 }  // namespace
 
-hipError_t launch_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int n_members, int block,
-                                hipStream_t s)
+hipError_t launch_batch_prepare(const BatchMember *mem, int n_members, long long step, int wpt,
+                                BatchTiles tiles, int *total, hipStream_t s)
 {
-  switch (block) {
-    case 128: hipLaunchKernelGGL((k_batch_prepare<128>), dim3(1), dim3(128), 0, s, ctl, mem, n_members); break;
-    case 256: hipLaunchKernelGGL((k_batch_prepare<256>), dim3(1), dim3(256), 0, s, ctl, mem, n_members); break;
-    case 512: hipLaunchKernelGGL((k_batch_prepare<512>), dim3(1), dim3(512), 0, s, ctl, mem, n_members); break;
-    default: return hipErrorInvalidValue;
-  }
+  hipLaunchKernelGGL(k_batch_prepare, dim3(1), dim3(1024), 0, s, mem, n_members, step, wpt, tiles, total);
   return hipGetLastError();
 }
 
-hipError_t launch_batch_step(BatchCtl *ctl, const BatchMember *mem, int block, int grid, hipStream_t s)
+hipError_t launch_batch_step(const BatchMember *mem, BatchTiles tiles, int n_tiles, const long long *base,
+                             int offset, int block, int wpt, hipStream_t s)
 {
-  switch (block) {
-    case 128: hipLaunchKernelGGL((k_batch_step<128>), dim3(grid), dim3(128), 0, s, ctl, mem); break;
-    case 256: hipLaunchKernelGGL((k_batch_step<256>), dim3(grid), dim3(256), 0, s, ctl, mem); break;
-    case 512: hipLaunchKernelGGL((k_batch_step<512>), dim3(grid), dim3(512), 0, s, ctl, mem); break;
+  if (n_tiles <= 0) return hipErrorInvalidValue;
+#define KA_BS(B, W) \
+  hipLaunchKernelGGL((k_batch_step<B, W>), dim3(n_tiles), dim3(B), 0, s, mem, tiles, base, offset)
+  switch (block * 4 + wpt) {
+    case 128 * 4 + 1: KA_BS(128, 1); break;
+    case 128 * 4 + 2: KA_BS(128, 2); break;
+    case 256 * 4 + 1: KA_BS(256, 1); break;
+    case 256 * 4 + 2: KA_BS(256, 2); break;
+    case 512 * 4 + 1: KA_BS(512, 1); break;
+    case 512 * 4 + 2: KA_BS(512, 2); break;
     default: return hipErrorInvalidValue;
   }
+#undef KA_BS
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(long long *base, int by, hipStream_t s)
+{
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, base, by);
   return hipGetLastError();
 }
 

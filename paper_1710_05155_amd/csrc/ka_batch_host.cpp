@@ -1,14 +1,16 @@
 // ka_batch_host.cpp -- host side of batched execution (include/ka.h, "Batches").
 //
-// A batch keeps a member table (pinned host copy + device copy) and a device control block
-// (global step, work-list prefix).  Step kernels advance the step themselves, so the host
-// only enqueues launches: whole captured graphs of step kernels, then single launches for
-// the remainder.  Progress events let ka_batch_poll detach finished members without
+// A batch keeps a member table (pinned host copy + device copy), a device step base, and
+// per segment (a run of steps with a fixed set of active members) a tile table built on the
+// device.  The host cuts the steps it enqueues into segments at the steps where members
+// finish or join, enqueues whole captured graphs of "G step kernels + base += G" and single
+// launches for the rest.  Progress events let ka_batch_poll detach finished members without
 // blocking.  Member descriptors never change while a member is active, and a slot is reused
 // only after its member's last step has completed on the device, so one pinned table and
 // whole-table asynchronous uploads are enough: a table that already holds members added
 // later is still correct for earlier steps, because a member is inactive outside
-// [s_begin, s_end).
+// [s_begin, s_end).  Tile tables alternate between two device buffers; stream order puts
+// each rebuild after every step that read the buffer before.
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -63,21 +65,34 @@ struct ka_batch {
   int cus = 256;
   ka::BatchMember *host_tab = nullptr;   // pinned
   ka::BatchMember *d_tab = nullptr;
-  ka::BatchCtl *d_ctl = nullptr;
+  long long *d_base = nullptr;           // device step base
+  int *d_total = nullptr;
+  int *d_tmember[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [buffer][wpt-1]
+  int *d_tlocal[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  int tcap[2][2] = {{0, 0}, {0, 0}};
   std::vector<ka_sim *> sims;            // per slot (nullptr = free)
   std::vector<int64_t> sweeps;           // per slot
+  std::vector<std::vector<int>> class_sizes;  // per slot, graphs only
   int n_members = 0;                     // highest used slot + 1
   int64_t step = 0;                      // steps enqueued
   int64_t done_step = 0;                 // steps known complete on the device
   std::deque<std::pair<hipEvent_t, int64_t>> progress;
   std::vector<hipEvent_t> event_pool;
-  bool dirty = false;
+  bool dirty = false;                    // member table changed since the last upload
   bool autotune = true, tuned = false;
-  int block = 256, grid = 0;
+  int block = 256;
   int graph_steps = 64;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  int g_block = 0, g_grid = 0, g_steps = 0;
+  // current segment
+  bool seg_valid = false;
+  int64_t seg_end = 0;
+  int buf = 0;
+  int T[2] = {0, 0};
+  // one captured graph per tile buffer
+  struct Graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    int T0 = -1, T1 = -1, block = 0, steps = 0;
+  } graphs[2];
 };
 
 namespace {
@@ -94,71 +109,149 @@ hipEvent_t take_event(ka_batch *b)
   return e;
 }
 
-int full_grid(const ka_batch *b, int block)
+int tiles_per_plane(const ka_batch *b, int k, int block)
 {
-  // step kernels hold up to 16 waves per CU
-  return b->cus * std::max(1, 16 / (block / 64));
+  const ka::BatchMember &m = b->host_tab[k];
+  if (m.kind == 0) {
+    const int nsub = m.d == 2 ? 4 : 16;
+    const int threads = nsub * 64 * ((m.P + 63) / 64);
+    return (threads + block - 1) / block;
+  }
+  int biggest = 0;
+  for (int c : b->class_sizes[(size_t)k]) biggest = std::max(biggest, c);
+  return (biggest + block - 1) / block;
 }
 
-hipError_t upload(ka_batch *b)
+bool active_at(const ka_batch *b, int k, int64_t s)
 {
-  hipError_t e = hipMemcpyAsync(b->d_tab, b->host_tab, sizeof(ka::BatchMember) * (size_t)std::max(1, b->n_members),
-                                hipMemcpyHostToDevice, b->stream);
-  if (e == hipSuccess) e = ka::launch_batch_prepare(b->d_ctl, b->d_tab, b->n_members, b->block, b->stream);
-  if (e == hipSuccess) b->dirty = false;
+  return b->sims[(size_t)k] && b->host_tab[k].s_begin <= s && s < b->host_tab[k].s_end;
+}
+
+void drop_graph(ka_batch::Graph &g)
+{
+  if (g.x) (void)hipGraphExecDestroy(g.x);
+  if (g.g) (void)hipGraphDestroy(g.g);
+  g = ka_batch::Graph();
+}
+
+hipError_t grow(ka_batch *b, int buf, int w, int need)
+{
+  if (need <= b->tcap[buf][w]) return hipSuccess;
+  // grow-only; earlier steps may still read the old buffer
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return e;
+  const int cap = std::max(need, 2 * b->tcap[buf][w]);
+  drop_graph(b->graphs[buf]);
+  (void)hipFree(b->d_tmember[buf][w]);
+  (void)hipFree(b->d_tlocal[buf][w]);
+  b->d_tmember[buf][w] = b->d_tlocal[buf][w] = nullptr;
+  b->tcap[buf][w] = 0;
+  e = hipMalloc((void **)&b->d_tmember[buf][w], sizeof(int) * (size_t)cap);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_tlocal[buf][w], sizeof(int) * (size_t)cap);
+  if (e == hipSuccess) b->tcap[buf][w] = cap;
   return e;
 }
 
-void drop_graph(ka_batch *b)
+// Start the segment beginning at the current step: upload the member table if it changed,
+// build the tile tables of the active members, and find where the segment ends.
+hipError_t new_segment(ka_batch *b)
 {
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
-  b->gexec = nullptr;
-  b->graph = nullptr;
-  b->g_steps = 0;
+  hipError_t e = hipSuccess;
+  if (b->dirty) {
+    for (int k = 0; k < b->n_members; ++k)
+      if (b->sims[(size_t)k]) b->host_tab[k].tiles_per_plane = tiles_per_plane(b, k, b->block);
+    e = hipMemcpyAsync(b->d_tab, b->host_tab, sizeof(ka::BatchMember) * (size_t)std::max(1, b->n_members),
+                       hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return e;
+    b->dirty = false;
+  }
+  const int64_t S = b->step;
+  int T[2] = {0, 0};
+  int64_t end = INT64_MAX;
+  for (int k = 0; k < b->n_members; ++k) {
+    if (!active_at(b, k, S)) continue;
+    const ka::BatchMember &m = b->host_tab[k];
+    T[m.wpt - 1] += m.planes * m.tiles_per_plane;
+    end = std::min<int64_t>(end, m.s_end);
+  }
+  b->buf ^= 1;
+  for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+    b->T[w] = T[w];
+    if (T[w] == 0) continue;
+    e = grow(b, b->buf, w, T[w]);
+    if (e == hipSuccess) {
+      ka::BatchTiles tt{b->d_tmember[b->buf][w], b->d_tlocal[b->buf][w]};
+      e = ka::launch_batch_prepare(b->d_tab, b->n_members, S, w + 1, tt, b->d_total, b->stream);
+    }
+  }
+  b->seg_end = end;
+  b->seg_valid = e == hipSuccess;
+  return e;
 }
 
-hipError_t ensure_graph(ka_batch *b)
+hipError_t launch_steps(ka_batch *b, int count)
 {
-  if (b->gexec && b->g_block == b->block && b->g_grid == b->grid && b->g_steps == b->graph_steps) return hipSuccess;
-  drop_graph(b);
-  hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-  if (e != hipSuccess) return e;
-  hipError_t le = hipSuccess;
-  for (int k = 0; k < b->graph_steps && le == hipSuccess; ++k)
-    le = ka::launch_batch_step(b->d_ctl, b->d_tab, b->block, b->grid, b->stream);
-  e = hipStreamEndCapture(b->stream, &b->graph);
-  if (le != hipSuccess) e = le;
-  if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
-  if (e != hipSuccess) {
-    drop_graph(b);
-    return e;
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < count && e == hipSuccess; ++q)
+    for (int w = 0; w < 2 && e == hipSuccess; ++w)
+      if (b->T[w] > 0) {
+        ka::BatchTiles tt{b->d_tmember[b->buf][w], b->d_tlocal[b->buf][w]};
+        e = ka::launch_batch_step(b->d_tab, tt, b->T[w], b->d_base, q, b->block, w + 1, b->stream);
+      }
+  if (e == hipSuccess) e = ka::launch_batch_advance(b->d_base, count, b->stream);
+  return e;
+}
+
+hipError_t launch_graph(ka_batch *b)
+{
+  ka_batch::Graph &g = b->graphs[b->buf];
+  if (!(g.x && g.T0 == b->T[0] && g.T1 == b->T[1] && g.block == b->block && g.steps == b->graph_steps)) {
+    drop_graph(g);
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = launch_steps(b, b->graph_steps);
+    e = hipStreamEndCapture(b->stream, &g.g);
+    if (le != hipSuccess) e = le;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.x, g.g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      drop_graph(g);
+      return e;
+    }
+    g.T0 = b->T[0];
+    g.T1 = b->T[1];
+    g.block = b->block;
+    g.steps = b->graph_steps;
   }
-  b->g_block = b->block;
-  b->g_grid = b->grid;
-  b->g_steps = b->graph_steps;
-  return hipSuccess;
+  return hipGraphLaunch(g.x, b->stream);
 }
 
 hipError_t enqueue_steps(ka_batch *b, int64_t n)
 {
   hipError_t e = hipSuccess;
-  if (b->dirty) e = upload(b);
-  if (e != hipSuccess) return e;
-  int64_t left = n;
-  if (b->graph_steps > 0 && left >= b->graph_steps) {
-    e = ensure_graph(b);
-    while (e == hipSuccess && left >= b->graph_steps) {
-      e = hipGraphLaunch(b->gexec, b->stream);
-      left -= b->graph_steps;
+  while (n > 0 && e == hipSuccess) {
+    if (!b->seg_valid || b->dirty || b->step >= b->seg_end) {
+      e = new_segment(b);
+      if (e != hipSuccess) break;
     }
-  }
-  while (e == hipSuccess && left > 0) {
-    e = ka::launch_batch_step(b->d_ctl, b->d_tab, b->block, b->grid, b->stream);
-    --left;
+    int64_t chunk = std::min<int64_t>(n, b->seg_end - b->step);
+    if (b->T[0] == 0 && b->T[1] == 0) {
+      e = ka::launch_batch_advance(b->d_base, (int)std::min<int64_t>(chunk, 1 << 30), b->stream);
+    } else {
+      int64_t left = chunk;
+      while (e == hipSuccess && b->graph_steps > 0 && left >= b->graph_steps) {
+        e = launch_graph(b);
+        left -= b->graph_steps;
+      }
+      while (e == hipSuccess && left > 0) {
+        const int r = (int)std::min<int64_t>(left, 1024);
+        e = launch_steps(b, r);
+        left -= r;
+      }
+    }
+    b->step += chunk;
+    n -= chunk;
   }
   if (e != hipSuccess) return e;
-  b->step += n;
   hipEvent_t ev = take_event(b);
   e = hipEventRecord(ev, b->stream);
   if (e != hipSuccess) return e;
@@ -170,57 +263,47 @@ int64_t max_classes(const ka_batch *b)
 {
   int64_t c = 1;
   for (int k = 0; k < b->n_members; ++k)
-    if (b->sims[k] && b->host_tab[k].s_end > b->step) c = std::max<int64_t>(c, b->host_tab[k].C);
+    if (b->sims[(size_t)k] && b->host_tab[k].s_end > b->step) c = std::max<int64_t>(c, b->host_tab[k].C);
   return c;
 }
 
-// Time equal numbers of real steps under each candidate launch shape and keep the fastest.
-// The steps are the batch's own work: results do not depend on the launch shape.
+// Time equal numbers of real steps with each workgroup size (tile size) and keep the
+// fastest.  The steps are the batch's own work: results do not depend on the tile size.
 hipError_t autotune(ka_batch *b, int64_t &n_steps)
 {
   const int blocks[3] = {128, 256, 512};
-  struct Cand { int block, grid; float ms; };
-  std::vector<Cand> cands;
-  for (int bl : blocks) {
-    const int fg = full_grid(b, bl);
-    for (int mul2 : {1, 2, 4}) cands.push_back({bl, fg * mul2 / 2, 0.f});
-  }
-  const int64_t probe = std::min<int64_t>(2 * max_classes(b), n_steps / (int64_t)(cands.size() + 1));
-  if (probe < 4) return hipSuccess;  // too little work to tune on; keep the default shape
+  const int64_t probe = std::min<int64_t>(2 * max_classes(b), n_steps / 4);
+  if (probe < 4) return hipSuccess;  // too little work to tune on; keep the default size
+  float ms[3] = {0.f, 0.f, 0.f};
   std::vector<std::pair<hipEvent_t, hipEvent_t>> evs;
-  for (auto &c : cands) {
-    if (c.block != b->block) {
-      b->block = c.block;
+  for (int q = 0; q < 3; ++q) {
+    if (b->block != blocks[q]) {
+      b->block = blocks[q];
       b->dirty = true;
     }
-    b->grid = c.grid;
-    hipError_t e = hipSuccess;
-    if (b->dirty) e = upload(b);
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (e == hipSuccess) e = hipEventCreate(&e0);
+    hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipEventRecord(e0, b->stream);
-    for (int64_t q = 0; q < probe && e == hipSuccess; ++q)
-      e = ka::launch_batch_step(b->d_ctl, b->d_tab, b->block, b->grid, b->stream);
+    if (e == hipSuccess) e = enqueue_steps(b, probe);
     if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
     if (e != hipSuccess) return e;
     evs.emplace_back(e0, e1);
-    b->step += probe;
     n_steps -= probe;
   }
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return e;
-  size_t best = 0;
-  for (size_t q = 0; q < cands.size(); ++q) {
-    (void)hipEventElapsedTime(&cands[q].ms, evs[q].first, evs[q].second);
+  int best = 0;
+  for (int q = 0; q < 3; ++q) {
+    (void)hipEventElapsedTime(&ms[q], evs[q].first, evs[q].second);
     (void)hipEventDestroy(evs[q].first);
     (void)hipEventDestroy(evs[q].second);
-    if (cands[q].ms < cands[best].ms) best = q;
+    if (ms[q] < ms[best]) best = q;
   }
-  b->done_step = b->step;
-  if (b->block != cands[best].block) b->dirty = true;
-  b->block = cands[best].block;
-  b->grid = cands[best].grid;
+  if (b->block != blocks[best]) {
+    b->block = blocks[best];
+    b->dirty = true;
+  }
   b->tuned = true;
   return hipSuccess;
 }
@@ -263,6 +346,7 @@ extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
   b->capacity = capacity;
   b->sims.assign((size_t)capacity, nullptr);
   b->sweeps.assign((size_t)capacity, 0);
+  b->class_sizes.assign((size_t)capacity, std::vector<int>());
   hipError_t e = hipSuccess;
   if (hip_stream) {
     b->stream = (hipStream_t)hip_stream;
@@ -272,21 +356,22 @@ extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
   }
   if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_tab, sizeof(ka::BatchMember) * (size_t)capacity, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc((void **)&b->d_tab, sizeof(ka::BatchMember) * (size_t)capacity);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_ctl, sizeof(ka::BatchCtl));
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_base, sizeof(long long));
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_total, sizeof(int));
   if (e == hipSuccess) {
     std::memset(b->host_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity);
-    e = hipMemsetAsync(b->d_ctl, 0, sizeof(ka::BatchCtl), b->stream);
+    e = hipMemsetAsync(b->d_base, 0, sizeof(long long), b->stream);
   }
   if (e == hipSuccess) e = hipMemsetAsync(b->d_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity, b->stream);
   if (e != hipSuccess) {
     if (b->host_tab) (void)hipHostFree(b->host_tab);
     (void)hipFree(b->d_tab);
-    (void)hipFree(b->d_ctl);
+    (void)hipFree(b->d_base);
+    (void)hipFree(b->d_total);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return bhip(e, "ka_batch_create");
   }
-  b->grid = full_grid(b, b->block);
   b->dirty = true;
   *out = b;
   return KA_OK;
@@ -334,6 +419,9 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
   m.t0 = (uint32_t)s->t;
   m.s_begin = b->step;
   m.s_end = b->step + (int64_t)s->C * n_sweeps;
+  b->class_sizes[(size_t)k].clear();
+  if (!s->lattice)
+    for (int c = 0; c < s->C; ++c) b->class_sizes[(size_t)k].push_back(s->class_start[(size_t)c + 1] - s->class_start[(size_t)c]);
   b->host_tab[k] = m;
   b->sims[(size_t)k] = s;
   b->sweeps[(size_t)k] = n_sweeps;
@@ -350,8 +438,7 @@ extern "C" int ka_batch_run(ka_batch *b, int64_t n_steps)
   if (n_steps <= 0) return KA_OK;
   Guard dg(b->device);
   hipError_t e = hipSuccess;
-  if (b->dirty) e = upload(b);
-  if (e == hipSuccess && b->autotune && !b->tuned) e = autotune(b, n_steps);
+  if (b->autotune && !b->tuned) e = autotune(b, n_steps);
   if (e == hipSuccess && n_steps > 0) e = enqueue_steps(b, n_steps);
   if (e != hipSuccess) return bhip(e, "ka_batch_run");
   return KA_OK;
@@ -414,11 +501,6 @@ extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
       b->block = (int)value;
       b->autotune = false;
       return KA_OK;
-    case KA_BOPT_GRID:
-      if (value < 1 || value > (1 << 20)) return bfail(KA_EINVAL, "grid out of range");
-      b->grid = (int)value;
-      b->autotune = false;
-      return KA_OK;
     case KA_BOPT_GRAPH_STEPS:
       if (value < 0 || value > 4096) return bfail(KA_EINVAL, "graph steps must be in [0, 4096]");
       b->graph_steps = (int)value;
@@ -428,7 +510,7 @@ extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
   }
 }
 
-extern "C" int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *grid)
+extern "C" int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *tiles)
 {
   if (!b) return bfail(KA_EINVAL, "batch is NULL");
   int active = 0;
@@ -436,7 +518,7 @@ extern "C" int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int
   if (step) *step = b->step;
   if (members) *members = active;
   if (block) *block = b->block;
-  if (grid) *grid = b->grid;
+  if (tiles) *tiles = b->T[0] + b->T[1];
   return KA_OK;
 }
 
@@ -446,12 +528,19 @@ extern "C" void ka_batch_free(ka_batch *b)
   (void)ka_batch_wait_all(b);
   Guard dg(b->device);
   (void)hipStreamSynchronize(b->stream);
-  drop_graph(b);
+  drop_graph(b->graphs[0]);
+  drop_graph(b->graphs[1]);
   for (auto &pr : b->progress) (void)hipEventDestroy(pr.first);
   for (hipEvent_t ev : b->event_pool) (void)hipEventDestroy(ev);
+  for (int q = 0; q < 2; ++q)
+    for (int w = 0; w < 2; ++w) {
+      (void)hipFree(b->d_tmember[q][w]);
+      (void)hipFree(b->d_tlocal[q][w]);
+    }
   (void)hipHostFree(b->host_tab);
   (void)hipFree(b->d_tab);
-  (void)hipFree(b->d_ctl);
+  (void)hipFree(b->d_base);
+  (void)hipFree(b->d_total);
   if (b->own_stream) (void)hipStreamDestroy(b->stream);
   delete b;
 }

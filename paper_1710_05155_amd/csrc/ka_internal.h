@@ -138,19 +138,21 @@ struct BatchMember {
   int z, m, C, planes, wpt;
   uint32_t key0, key1;
   uint32_t t0;
-  int pad0;
+  int tiles_per_plane;         // tiles of BLOCK threads per plane (graphs: largest class)
   long long s_begin, s_end;
 };
 
-struct BatchCtl {
-  long long step;              // global step the next step kernel executes
-  unsigned done;               // blocks finished in the current launch
-  int n_members;
-  int prefix[kBatchMaxMembers + 1];   // tile prefix over members for `step`
+// Work list of one segment (steps between membership changes): tile q belongs to member
+// tile_member[q] as its tile tile_local[q].  Built on the device by the prepare kernel.
+struct BatchTiles {
+  int *member;
+  int *local;
 };
 
-hipError_t launch_batch_prepare(BatchCtl *ctl, const BatchMember *mem, int n_members, int block,
-                                hipStream_t s);
-hipError_t launch_batch_step(BatchCtl *ctl, const BatchMember *mem, int block, int grid, hipStream_t s);
+hipError_t launch_batch_prepare(const BatchMember *mem, int n_members, long long step, int wpt,
+                                BatchTiles tiles, int *total, hipStream_t s);
+hipError_t launch_batch_step(const BatchMember *mem, BatchTiles tiles, int n_tiles, const long long *base,
+                             int offset, int block, int wpt, hipStream_t s);
+hipError_t launch_batch_advance(long long *base, int by, hipStream_t s);
 
 }  // namespace ka

@@ -32,7 +32,6 @@ SYMBOLS = (
 )
 KA_BOPT_AUTOTUNE = 1
 KA_BOPT_BLOCK = 2
-KA_BOPT_GRID = 3
 KA_BOPT_GRAPH_STEPS = 4
 
 
@@ -370,10 +369,10 @@ def ka_batch_info(b: Batch):
     step = ctypes.c_int64()
     members = ctypes.c_int()
     block = ctypes.c_int()
-    grid = ctypes.c_int()
+    tiles = ctypes.c_int()
     _check(load().ka_batch_info(b.handle, ctypes.byref(step), ctypes.byref(members), ctypes.byref(block),
-                                ctypes.byref(grid)))
-    return step.value, members.value, block.value, grid.value
+                                ctypes.byref(tiles)))
+    return step.value, members.value, block.value, tiles.value
 
 
 def ka_batch_free(b: Batch) -> None:
@@ -406,15 +405,4 @@ def derived_observables(N: int, K: int, overlap, persistence):
     return C, chi4, P
 
 
-def log_time_grid(t_max: int, per_decade: int = 10) -> list[int]:
-    """0 and the distinct floor(10^(k/per_decade)) <= t_max: a log-spaced observation grid."""
-    import math
-    out = {0}
-    k = 0
-    while True:
-        v = int(math.floor(10.0 ** (k / per_decade)))
-        if v > t_max:
-            break
-        out.add(v)
-        k += 1
-    return sorted(out)
+from .workloads import log_time_grid  # noqa: E402,F401  (observation grid recipe)

@@ -93,9 +93,9 @@ def _assert_same(states, solo):
 
 @pytest.mark.parametrize("options", [
     (),                                                                         # autotuned, graphs
-    ((ka.KA_BOPT_BLOCK, 128), (ka.KA_BOPT_GRID, 7), (ka.KA_BOPT_GRAPH_STEPS, 0)),
-    ((ka.KA_BOPT_BLOCK, 512), (ka.KA_BOPT_GRID, 3000), (ka.KA_BOPT_GRAPH_STEPS, 5)),
-    ((ka.KA_BOPT_BLOCK, 256), (ka.KA_BOPT_GRID, 1), (ka.KA_BOPT_GRAPH_STEPS, 64)),
+    ((ka.KA_BOPT_BLOCK, 128), (ka.KA_BOPT_GRAPH_STEPS, 0)),
+    ((ka.KA_BOPT_BLOCK, 512), (ka.KA_BOPT_GRAPH_STEPS, 5)),
+    ((ka.KA_BOPT_BLOCK, 256), (ka.KA_BOPT_GRAPH_STEPS, 64)),
 ])
 def test_batch_members_equal_solo(graphs, solo, options):
     _say(f"batch options {options}")
