@@ -199,6 +199,58 @@ int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, in
 /* Finish all members (as ka_batch_wait_all) and release the batch. */
 void ka_batch_free(ka_batch *b);
 
+/* ------------------------------------------------------------------------------------ */
+/* Serving: a job server with continuous batching.  A worker thread owns one stream and  */
+/* one batch; submitted jobs wait in FIFO order until a slot is free and their device    */
+/* footprint (ka_footprint) fits the budget, then are initialised on the device and join */
+/* the batch, so jobs that arrive while others run share the same step kernels.  A job's */
+/* observation times cut it into batch segments; at each one the per-replica counts of   */
+/* ka_observe are taken on the device and copied back without stopping the batch.  Each  */
+/* job's results are bit-identical to running it alone (same kernels, same counters).    */
+/* ------------------------------------------------------------------------------------ */
+typedef struct ka_server ka_server;
+
+typedef struct {
+  const ka_graph *graph;     /* borrowed: must stay valid until the job has started     */
+  int m;                     /* activation number                                       */
+  double rho;                /* density; K = floor(rho*N + 1/2)                          */
+  uint64_t seed;
+  int n_replicas;            /* multiple of 64                                          */
+  int64_t n_sweeps;          /* total sweeps                                            */
+  const int64_t *obs_times;  /* sweep indices in [0, n_sweeps], non-decreasing; copied;  */
+  int n_obs;                 /* NULL/0: one observation at n_sweeps                     */
+  int keep_sim;              /* 1: keep the final sim for ka_server_take_sim            */
+} ka_job_desc;
+
+/* Server with a device-memory budget (bytes) and at most max_active concurrent jobs
+ * (1..1024), on hip_stream (NULL: its own stream).  Starts the worker thread. */
+int ka_server_create(size_t device_budget, int max_active, void *hip_stream, ka_server **out);
+
+/* Queue a job (thread-safe, non-blocking).  KA_EINVAL if it can never fit the budget. */
+int ka_server_submit(ka_server *sv, const ka_job_desc *job, int64_t *job_id);
+
+/* Ids of jobs completed since the last call (at most max_ids; thread-safe). */
+int ka_server_poll(ka_server *sv, int64_t *job_ids, int max_ids, int *n);
+
+/* Results of a completed job: counts int64 [n_obs][n_replicas] each (any may be NULL),
+ * and seconds from submission to admission and to completion.  KA_ESTATE if not done. */
+int ka_server_result(ka_server *sv, int64_t job_id, int64_t *density, int64_t *overlap,
+                     int64_t *persistence, double *wait_s, double *latency_s);
+
+/* Hand over the final sim of a completed job submitted with keep_sim (caller frees it). */
+int ka_server_take_sim(ka_server *sv, int64_t job_id, ka_sim **out);
+
+/* Block until every submitted job has completed. */
+int ka_server_wait_idle(ka_server *sv);
+
+/* Counters: jobs completed, site-replica attempts completed, peak concurrent jobs, peak
+ * device bytes in use (any may be NULL). */
+int ka_server_stats(ka_server *sv, int64_t *jobs_done, double *attempts, int *peak_active,
+                    size_t *peak_bytes);
+
+/* Stop the worker after the queued jobs complete, and release everything. */
+void ka_server_free(ka_server *sv);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char *ka_last_error(void);
 

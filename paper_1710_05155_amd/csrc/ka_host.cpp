@@ -835,6 +835,22 @@ extern "C" int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *over
   return KA_OK;
 }
 
+// Enqueue the counts of ka_observe at the current t on the sim's stream, copied into
+// host_out (pinned, 3 * R values: density, overlap, persistence), without synchronising.
+int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out)
+{
+  int rc = check_sim(s);
+  if (rc) return rc;
+  DeviceGuard dg(s->device);
+  hipError_t e = ensure_obs_buffers(s, 1);
+  const size_t bytes = 3u * (size_t)s->R * sizeof(unsigned long long);
+  if (e == hipSuccess) e = hipMemsetAsync(s->counts, 0, bytes, s->stream);
+  if (e == hipSuccess) e = observe_global(s, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(host_out, s->counts, bytes, hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(e, "observe");
+  return KA_OK;
+}
+
 extern "C" int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, int64_t *t)
 {
   int rc = check_sim(s);

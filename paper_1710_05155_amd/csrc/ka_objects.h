@@ -68,4 +68,6 @@ struct ka_sim {
 void ka_set_error(const char *msg);
 // Finish the batch work of a member that is being freed.
 int ka_batch_release_member(ka_batch *b, ka_sim *s);
+// Counts of ka_observe enqueued on the sim's stream into pinned host memory (3 * R values).
+int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out);
 

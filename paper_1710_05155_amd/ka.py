@@ -29,7 +29,24 @@ SYMBOLS = (
     "ka_timing", "ka_sim_path", "ka_free", "ka_last_error",
     "ka_batch_create", "ka_batch_add", "ka_batch_run", "ka_batch_steps_left", "ka_batch_poll",
     "ka_batch_wait_all", "ka_batch_set_option", "ka_batch_info", "ka_batch_free",
+    "ka_server_create", "ka_server_submit", "ka_server_poll", "ka_server_result", "ka_server_take_sim",
+    "ka_server_wait_idle", "ka_server_stats", "ka_server_free",
 )
+
+
+class JobDesc(ctypes.Structure):
+    """ka_job_desc (include/ka.h)."""
+    _fields_ = [
+        ("graph", ctypes.c_void_p),
+        ("m", ctypes.c_int),
+        ("rho", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("n_replicas", ctypes.c_int),
+        ("n_sweeps", ctypes.c_int64),
+        ("obs_times", ctypes.c_void_p),
+        ("n_obs", ctypes.c_int),
+        ("keep_sim", ctypes.c_int),
+    ]
 KA_BOPT_AUTOTUNE = 1
 KA_BOPT_BLOCK = 2
 KA_BOPT_GRAPH_STEPS = 4
@@ -88,6 +105,14 @@ def load():
         "ka_batch_set_option": ([P, I, I64], I),
         "ka_batch_info": ([P, P, P, P, P], I),
         "ka_batch_free": ([P], None),
+        "ka_server_create": ([ctypes.c_size_t, I, P, PP], I),
+        "ka_server_submit": ([P, ctypes.POINTER(JobDesc), P], I),
+        "ka_server_poll": ([P, P, I, P], I),
+        "ka_server_result": ([P, I64, P, P, P, P, P], I),
+        "ka_server_take_sim": ([P, I64, PP], I),
+        "ka_server_wait_idle": ([P], I),
+        "ka_server_stats": ([P, P, P, P, P], I),
+        "ka_server_free": ([P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -377,6 +402,89 @@ def ka_batch_info(b: Batch):
 
 def ka_batch_free(b: Batch) -> None:
     b.free()
+
+
+# ------------------------------------------------------------------------------ serving
+class Server:
+    """Owning handle of a ka_server.  Keeps the graphs of queued jobs alive."""
+
+    def __init__(self, handle, stream):
+        self._h = handle
+        self.stream = stream
+        self.jobs = {}   # id -> (graph, n_obs, R)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free(self):
+        if self._h and _lib is not None:
+            _lib.ka_server_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+def ka_server_create(device_budget: int, max_active: int, stream=None) -> Server:
+    h = ctypes.c_void_p()
+    _check(load().ka_server_create(int(device_budget), int(max_active), _stream_handle(stream), ctypes.byref(h)))
+    return Server(h, stream)
+
+
+def ka_server_submit(sv: Server, graph: Graph, m: int, rho: float, seed: int, n_replicas: int,
+                     n_sweeps: int, obs_times=None, keep_sim: bool = False) -> int:
+    obs = None if obs_times is None else np.ascontiguousarray(np.asarray(obs_times, dtype=np.int64))
+    d = JobDesc(graph.handle, int(m), float(rho), int(seed), int(n_replicas), int(n_sweeps),
+                _ptr(obs) if obs is not None else None, 0 if obs is None else int(obs.shape[0]),
+                1 if keep_sim else 0)
+    jid = ctypes.c_int64()
+    _check(load().ka_server_submit(sv.handle, ctypes.byref(d), ctypes.byref(jid)))
+    sv.jobs[jid.value] = (graph, 1 if obs is None else int(obs.shape[0]), int(n_replicas))
+    return jid.value
+
+
+def ka_server_poll(sv: Server, max_ids: int = 4096) -> list:
+    ids = np.empty(max_ids, dtype=np.int64)
+    n = ctypes.c_int()
+    _check(load().ka_server_poll(sv.handle, _ptr(ids), max_ids, ctypes.byref(n)))
+    return [int(x) for x in ids[: n.value]]
+
+
+def ka_server_result(sv: Server, job_id: int):
+    _, n_obs, R = sv.jobs[job_id]
+    dens = np.empty((n_obs, R), dtype=np.int64)
+    ov = np.empty((n_obs, R), dtype=np.int64)
+    pers = np.empty((n_obs, R), dtype=np.int64)
+    wait = ctypes.c_double()
+    lat = ctypes.c_double()
+    _check(load().ka_server_result(sv.handle, int(job_id), _ptr(dens), _ptr(ov), _ptr(pers), ctypes.byref(wait),
+                                   ctypes.byref(lat)))
+    return {"density": dens, "overlap": ov, "persistence": pers, "wait_s": wait.value, "latency_s": lat.value}
+
+
+def ka_server_take_sim(sv: Server, job_id: int) -> Sim:
+    h = ctypes.c_void_p()
+    _check(load().ka_server_take_sim(sv.handle, int(job_id), ctypes.byref(h)))
+    return Sim(h, sv.jobs[job_id][0], sv.stream)
+
+
+def ka_server_wait_idle(sv: Server) -> None:
+    _check(load().ka_server_wait_idle(sv.handle))
+
+
+def ka_server_stats(sv: Server):
+    done = ctypes.c_int64()
+    att = ctypes.c_double()
+    peak = ctypes.c_int()
+    pbytes = ctypes.c_size_t()
+    _check(load().ka_server_stats(sv.handle, ctypes.byref(done), ctypes.byref(att), ctypes.byref(peak),
+                                  ctypes.byref(pbytes)))
+    return {"jobs_done": done.value, "attempts": att.value, "peak_active": peak.value, "peak_bytes": pbytes.value}
+
+
+def ka_server_free(sv: Server) -> None:
+    sv.free()
 
 
 # ------------------------------------------------------------------------------ host helpers

@@ -1,0 +1,113 @@
+"""Serving with continuous batching: jobs submitted while others run are admitted as slots
+and device memory free up, share the batch's step kernels, and each job's observations and
+final state are bit-identical to running it alone."""
+import random
+import time
+
+import numpy as np
+import pytest
+
+from paper_1710_05155_amd import ka
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+
+
+JOBS = [
+    # graph key, m, rho, R, seed, sweeps, obs
+    (("lat", 2, 8), 2, 0.6, 64, 1, 12, [0, 3, 12]),
+    (("lat", 2, 16), 1, 0.5, 128, 2, 20, None),
+    (("lat", 3, 8), 3, 0.8, 256, 3, 9, [0, 1, 2, 5, 9]),
+    (("rrg", 300, 4), 2, 0.65, 64, 4, 15, [7, 15]),
+    (("rrg", 64, 3), 1, 0.5, 192, 5, 30, [0, 30]),
+    (("lat", 2, 64), 2, 0.7, 64, 6, 25, [0, 5, 10, 15, 20, 25]),
+    (("rrg", 500, 5), 3, 0.7, 128, 7, 8, None),
+    (("lat", 3, 12), 2, 0.6, 64, 8, 6, [6]),
+    (("rrg", 200, 6), 3, 0.8, 64, 9, 11, [0, 11]),
+    (("lat", 2, 12), 3, 0.85, 320, 10, 4, [0, 2, 4]),
+    (("lat", 2, 8), 0, 0.4, 64, 11, 0, None),
+    (("rrg", 1000, 4), 2, 0.6, 64, 12, 18, [9, 18]),
+]
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    out = {}
+    for j in JOBS:
+        key = j[0]
+        if key in out:
+            continue
+        out[key] = ka.ka_graph_lattice(key[1], key[2]) if key[0] == "lat" else ka.ka_graph_rrg(key[1], key[2], 40 + key[1])
+    return out
+
+
+def _solo(g, m, rho, R, seed, sweeps, obs):
+    s = ka.ka_init(g, m, rho, seed, R)
+    times = obs if obs is not None else [sweeps]
+    dens, ov, pers = ka.ka_run(s, times)
+    if s.t < sweeps:
+        ka.ka_sweep(s, sweeps - s.t)
+    state = ka.ka_get_state(s)
+    s.free()
+    return (dens, ov, pers), state
+
+
+def _run_server(graphs, budget, max_active, jitter):
+    sv = ka.ka_server_create(budget, max_active)
+    rng = random.Random(3)
+    ids = []
+    for (key, m, rho, R, seed, sweeps, obs) in JOBS:
+        ids.append(ka.ka_server_submit(sv, graphs[key], m, rho, seed, R, sweeps, obs_times=obs, keep_sim=True))
+        if jitter:
+            time.sleep(rng.uniform(0.0, 0.004))
+    ka.ka_server_wait_idle(sv)
+    out = []
+    for jid in ids:
+        res = ka.ka_server_result(sv, jid)
+        sim = ka.ka_server_take_sim(sv, jid)
+        out.append((res, ka.ka_get_state(sim)))
+        sim.free()
+    stats = ka.ka_server_stats(sv)
+    done = set(ka.ka_server_poll(sv))
+    sv.free()
+    assert done == set(ids)
+    return out, stats
+
+
+@pytest.mark.parametrize("budget,max_active,jitter", [(1 << 34, 64, True), (1 << 34, 3, False)])
+def test_served_jobs_equal_solo(graphs, budget, max_active, jitter):
+    _say(f"serve budget={budget} max_active={max_active}")
+    served, stats = _run_server(graphs, budget, max_active, jitter)
+    assert stats["jobs_done"] == len(JOBS)
+    assert stats["peak_active"] <= max_active
+    for k, ((key, m, rho, R, seed, sweeps, obs), (res, state)) in enumerate(zip(JOBS, served)):
+        (dens, ov, pers), solo_state = _solo(graphs[key], m, rho, R, seed, sweeps, obs)
+        assert np.array_equal(res["density"], dens), k
+        assert np.array_equal(res["overlap"], ov), k
+        assert np.array_equal(res["persistence"], pers), k
+        for a, b in zip(state, solo_state):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), k
+        assert res["latency_s"] >= res["wait_s"] >= 0.0
+
+
+def test_admission_by_footprint(graphs):
+    """A budget that holds only the largest job alone still runs every job, within it."""
+    big = max(ka.ka_footprint(graphs[j[0]], j[3]) for j in JOBS)
+    budget = int(big * 1.05) + (1 << 20)
+    _say("serve: budget for the largest job")
+    served, stats = _run_server(graphs, budget, 64, False)
+    assert stats["peak_bytes"] <= budget
+    for k, ((key, m, rho, R, seed, sweeps, obs), (res, state)) in enumerate(zip(JOBS, served)):
+        (dens, ov, pers), solo_state = _solo(graphs[key], m, rho, R, seed, sweeps, obs)
+        assert np.array_equal(res["overlap"], ov) and np.array_equal(res["persistence"], pers), k
+
+
+def test_server_rejects_oversized_job(graphs):
+    sv = ka.ka_server_create(1 << 12, 4)
+    with pytest.raises(ka.KaError) as e:
+        ka.ka_server_submit(sv, graphs[("lat", 2, 64)], 2, 0.7, 1, 64, 10)
+    assert e.value.code == ka.KA_EINVAL
+    sv.free()
