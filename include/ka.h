@@ -71,6 +71,17 @@ int ka_graph_lattice(int d, int L, ka_graph **out);
  * Returns KA_ESTATE if no simple pairing is found within 10^6 attempts. */
 int ka_graph_rrg(int64_t N, int z, uint64_t graph_seed, ka_graph **out);
 
+/* Layered random graph (Sec. 5.2): M copies of the periodic lattice Z_L^d (d in {2, 3},
+ * L >= 3); for every bond (x, x+e_mu) the M links (x, a)-(x+e_mu, a) become
+ * (x, a)-(x+e_mu, P(a)) with P a uniform random permutation of the copies, independent per
+ * bond.  Vertex (x, a) has id a*L^d + i(x); rows sorted.  P of the bond with lattice edge id
+ * e = i*d + mu: Fisher-Yates (k = M-1 down to 1, swap k with U[0, k]) of 0..M-1 on the
+ * 32-bit words of Philox4x32-10(counter (e, 0xFFFFFFFD, s/4, 0), key graph_seed), word s =
+ * output s % 4, uniform integers by Lemire's method.  Canonical edges as for any graph;
+ * classes: the lattice class of the lifted bond when L % 4 == 0 (C = 4d), else the greedy
+ * distance-2 colouring.  M*L^d <= 2^28. */
+int ka_graph_layered(int d, int L, int M, uint64_t graph_seed, ka_graph **out);
+
 /* Any simple z-regular graph given as adjacency rows adj[N][z] (copied; z in [3, 6]).
  * KA_EINVAL if an entry is out of range, a self-loop, repeated, or not symmetric. */
 int ka_graph_from_adjacency(int64_t N, int z, const int32_t *adj, ka_graph **out);

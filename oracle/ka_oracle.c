@@ -426,3 +426,100 @@ int ko_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------------------ */
+/* Layered random graph (Sec. 5.2): M copies of the periodic lattice Z_L^d; for every     */
+/* bond (x, x+e_mu) of the base lattice the M links (x, a)-(x+e_mu, a) are replaced by    */
+/* (x, a)-(x+e_mu, P(a)) with P a uniformly random permutation of the M copies, drawn     */
+/* independently for every bond.  Vertex (x, a) has id a*N + i(x).  P for the bond with   */
+/* base edge id e = i*d + mu is a Fisher-Yates shuffle (k = M-1 down to 1, swap k and      */
+/* U[0,k]) of 0..M-1 driven by the words of Philox with counter (e, 0xFFFFFFFD, s/4, 0),  */
+/* word s = output s%4, key graph_seed, with Lemire's method for U[0,k].                  */
+/* Rows of adj are sorted ascending.  base_class[v*z + k] receives the lattice class of   */
+/* the bond that carries the k-th (sorted) neighbour link of v.                           */
+/* ------------------------------------------------------------------------------------ */
+static uint32_t ko_bond_word(uint64_t seed, uint32_t e, uint64_t s)
+{
+    uint32_t ctr[4] = {e, 0xFFFFFFFDu, (uint32_t)(s / 4), 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t out[4];
+    ko_philox(ctr, key, out);
+    return out[s % 4];
+}
+
+static uint32_t ko_bond_below(uint64_t seed, uint32_t e, uint64_t *s, uint32_t range)
+{
+    uint64_t prod = (uint64_t)ko_bond_word(seed, e, (*s)++) * range;
+    uint32_t low = (uint32_t)prod;
+    if (low < range) {
+        uint32_t threshold = (uint32_t)(-range) % range;
+        while (low < threshold) {
+            prod = (uint64_t)ko_bond_word(seed, e, (*s)++) * range;
+            low = (uint32_t)prod;
+        }
+    }
+    return (uint32_t)(prod >> 32);
+}
+
+int ko_layered(int d, int L, int M, uint64_t seed, int32_t *adj)
+{
+    if (d < 2 || d > 3 || L < 3 || M < 1) return -1;
+    int64_t N = 1;
+    for (int k = 0; k < d; ++k) N *= L;
+    int z = 2 * d;
+    int32_t *eu = (int32_t *)malloc(sizeof(int32_t) * N * d);
+    int32_t *ev = (int32_t *)malloc(sizeof(int32_t) * N * d);
+    /* the bonds of the base lattice (any L >= 3 gives distinct neighbours) */
+    for (int64_t i = 0; i < N; ++i) {
+        int x[3] = {0, 0, 0};
+        int64_t rest = i;
+        for (int k = 0; k < d; ++k) { x[k] = (int)(rest % L); rest /= L; }
+        for (int mu = 0; mu < d; ++mu) {
+            int up[3] = {x[0], x[1], x[2]};
+            up[mu] = (x[mu] + 1) % L;
+            int64_t iu = 0, stride = 1;
+            for (int k = 0; k < d; ++k) { iu += up[k] * stride; stride *= L; }
+            eu[i * d + mu] = (int32_t)i;
+            ev[i * d + mu] = (int32_t)iu;
+        }
+    }
+    int32_t *fill = (int32_t *)calloc((size_t)(N * M), sizeof(int32_t));
+    int32_t *perm = (int32_t *)malloc(sizeof(int32_t) * M);
+    for (int64_t e = 0; e < N * d; ++e) {
+        for (int a = 0; a < M; ++a) perm[a] = a;
+        uint64_t s = 0;
+        for (int k = M - 1; k >= 1; --k) {
+            uint32_t j = ko_bond_below(seed, (uint32_t)e, &s, (uint32_t)(k + 1));
+            int32_t t = perm[k]; perm[k] = perm[j]; perm[j] = t;
+        }
+        for (int a = 0; a < M; ++a) {
+            int64_t u = (int64_t)a * N + eu[e];
+            int64_t v = (int64_t)perm[a] * N + ev[e];
+            adj[u * z + fill[u]++] = (int32_t)v;
+            adj[v * z + fill[v]++] = (int32_t)u;
+        }
+    }
+    for (int64_t v = 0; v < N * M; ++v) qsort(adj + v * z, (size_t)z, sizeof(int32_t), ko_cmp_i32);
+    free(eu); free(ev); free(fill); free(perm);
+    return 0;
+}
+
+/* Class of each canonical edge of a layered graph by projection to the base lattice:
+ * the class of the base bond joining the two endpoints' sites (valid when L % 4 == 0). */
+void ko_layered_classes(int d, int L, int64_t N, int64_t E, const int32_t *eu, const int32_t *ev,
+                        int32_t *ecls)
+{
+    for (int64_t q = 0; q < E; ++q) {
+        int64_t iu = eu[q] % N, iv = ev[q] % N;
+        int xu[3] = {0, 0, 0}, xv[3] = {0, 0, 0};
+        int64_t ru = iu, rv = iv;
+        for (int k = 0; k < d; ++k) { xu[k] = (int)(ru % L); ru /= L; xv[k] = (int)(rv % L); rv /= L; }
+        int mu = 0;
+        for (int k = 0; k < d; ++k) if (xu[k] != xv[k]) mu = k;
+        /* the lower endpoint of the bond is the one whose +e_mu neighbour is the other */
+        const int *lo = ((xu[mu] + 1) % L == xv[mu]) ? xu : xv;
+        int others = 0;
+        for (int nu = 0; nu < d; ++nu) if (nu != mu) others += lo[nu];
+        ecls[q] = 4 * mu + ((lo[mu] + 2 * others) % 4);
+    }
+}

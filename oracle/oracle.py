@@ -50,6 +50,9 @@ def load():
         _lib.ko_accept_bit.restype = I32
         _lib.ko_run.argtypes = [I64, I32, P, I64, P, P, P, I32, I32, U64, I64, P, I64, I64, P, P]
         _lib.ko_threads.restype = I32
+        _lib.ko_layered.argtypes = [I32, I32, I32, U64, P]
+        _lib.ko_layered.restype = I32
+        _lib.ko_layered_classes.argtypes = [I32, I32, I64, I64, P, P, P]
     return _lib
 
 
@@ -134,6 +137,31 @@ def rrg(N: int, z: int, graph_seed: int) -> Graph:
     adj, _ = rrg_adjacency(N, z, graph_seed)
     g = graph_from_adjacency(adj)
     g.kind = "rrg"
+    return g
+
+
+def layered_adjacency(d: int, L: int, M: int, graph_seed: int) -> np.ndarray:
+    """Layered random graph (Sec. 5.2): M lattice copies, a random permutation per bond."""
+    lib = load()
+    N = L ** d * M
+    adj = np.empty((N, 2 * d), dtype=np.int32)
+    if lib.ko_layered(d, L, M, graph_seed, _p(adj)) != 0:
+        raise ValueError("oracle: bad layered graph arguments")
+    return adj
+
+
+def layered(d: int, L: int, M: int, graph_seed: int) -> Graph:
+    """Layered graph with canonical edges; classes by projection to the lattice when
+    L % 4 == 0, otherwise the greedy distance-2 colouring."""
+    lib = load()
+    adj = layered_adjacency(d, L, M, graph_seed)
+    g = graph_from_adjacency(adj)
+    if L % 4 == 0:
+        ecls = np.empty(g.E, dtype=np.int32)
+        lib.ko_layered_classes(d, L, L ** d, g.E, _p(g.eu), _p(g.ev), _p(ecls))
+        g.ecls = ecls
+        g.C = 4 * d
+    g.kind = "layered"
     return g
 
 

@@ -302,6 +302,96 @@ extern "C" int ka_graph_rrg(int64_t N, int z, uint64_t graph_seed, ka_graph **ou
   return KA_OK;
 }
 
+extern "C" int ka_graph_layered(int d, int L, int M, uint64_t graph_seed, ka_graph **out)
+{
+  if (!out) return fail(KA_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (d != 2 && d != 3) return fail(KA_EINVAL, "lattice dimension must be 2 or 3 (got %d)", d);
+  if (L < 3) return fail(KA_EINVAL, "lattice side must be >= 3 (got %d)", L);
+  if (M < 1) return fail(KA_EINVAL, "number of copies must be >= 1 (got %d)", M);
+  int64_t Nb = 1;
+  for (int k = 0; k < d; ++k) Nb *= L;
+  if (Nb * M > (1ll << 28)) return fail(KA_EINVAL, "layered graph too large (%lld sites)", (long long)(Nb * M));
+  ka_graph *g = new (std::nothrow) ka_graph;
+  if (!g) return fail(KA_ENOMEM, "host allocation failed");
+  const int z = 2 * d;
+  g->N = Nb * M;
+  g->z = z;
+  try {
+    g->adj.resize((size_t)g->N * z);
+  } catch (...) {
+    delete g;
+    return fail(KA_ENOMEM, "host allocation failed");
+  }
+  const int64_t stride[3] = {1, L, (int64_t)L * L};
+  std::vector<int> fill((size_t)g->N, 0);
+  std::vector<int32_t> perm((size_t)M);
+  for (int64_t i = 0; i < Nb; ++i) {
+    for (int mu = 0; mu < d; ++mu) {
+      const int x_mu = (int)((i / stride[mu]) % L);
+      const int64_t j = i + (x_mu + 1 < L ? stride[mu] : -(int64_t)(L - 1) * stride[mu]);
+      // permutation of the M copies for this bond (base edge id i*d + mu)
+      const uint64_t e = (uint64_t)(i * d + mu);
+      uint32_t words[4];
+      uint64_t next = 0, block = UINT64_MAX;
+      auto word = [&]() -> uint32_t {
+        const uint64_t q = next / 4;
+        if (q != block) {
+          const uint32_t ctr[4] = {(uint32_t)e, 0xFFFFFFFDu, (uint32_t)q, 0u};
+          philox_host(ctr, graph_seed, words);
+          block = q;
+        }
+        return words[next++ % 4];
+      };
+      auto below = [&](uint32_t range) -> uint32_t {  // Lemire's multiply-shift with rejection
+        uint64_t prod = (uint64_t)word() * range;
+        uint32_t low = (uint32_t)prod;
+        if (low < range) {
+          const uint32_t thresh = (uint32_t)(0u - range) % range;
+          while (low < thresh) {
+            prod = (uint64_t)word() * range;
+            low = (uint32_t)prod;
+          }
+        }
+        return (uint32_t)(prod >> 32);
+      };
+      for (int a = 0; a < M; ++a) perm[(size_t)a] = a;
+      for (int k = M - 1; k >= 1; --k) std::swap(perm[(size_t)k], perm[below((uint32_t)(k + 1))]);
+      for (int a = 0; a < M; ++a) {
+        const int64_t u = (int64_t)a * Nb + i, v = (int64_t)perm[(size_t)a] * Nb + j;
+        g->adj[(size_t)u * z + fill[(size_t)u]++] = (int32_t)v;
+        g->adj[(size_t)v * z + fill[(size_t)v]++] = (int32_t)u;
+      }
+    }
+  }
+  for (int64_t v = 0; v < g->N; ++v) std::sort(&g->adj[(size_t)v * z], &g->adj[(size_t)v * z] + z);
+  int rc = finish_general_graph(*g);
+  if (rc != KA_OK) {
+    delete g;
+    return rc;
+  }
+  if (L % 4 == 0) {
+    // Classes by projection to the lattice: an edge takes the class of the bond it lifts.
+    // Projection maps edges to edges, so distances can only shrink under it; two lifts of
+    // one bond share no site and no link.  The lattice classes therefore stay valid.
+    for (size_t q = 0; q < g->eu.size(); ++q) {
+      const int64_t iu = g->eu[q] % Nb, iv = g->ev[q] % Nb;
+      int mu = 0;
+      for (int k = 0; k < d; ++k)
+        if ((iu / stride[k]) % L != (iv / stride[k]) % L) mu = k;
+      const int64_t xu = (iu / stride[mu]) % L;
+      const int64_t lo = ((xu + 1) % L == (iv / stride[mu]) % L) ? iu : iv;
+      int others = 0;
+      for (int k = 0; k < d; ++k)
+        if (k != mu) others += (int)((lo / stride[k]) % L);
+      g->ecls[q] = 4 * mu + (int)((((lo / stride[mu]) % L) + 2 * others) & 3);
+    }
+    g->C = 4 * d;
+  }
+  *out = g;
+  return KA_OK;
+}
+
 extern "C" int ka_graph_from_adjacency(int64_t N, int z, const int32_t *adj, ka_graph **out)
 {
   if (!out || !adj) return fail(KA_EINVAL, "NULL argument");

@@ -23,7 +23,7 @@ KA_OPT_TIMING = 2
 
 # Every symbol include/ka.h declares.
 SYMBOLS = (
-    "ka_graph_lattice", "ka_graph_rrg", "ka_graph_from_adjacency", "ka_graph_info",
+    "ka_graph_lattice", "ka_graph_rrg", "ka_graph_layered", "ka_graph_from_adjacency", "ka_graph_info",
     "ka_graph_export", "ka_graph_free", "ka_footprint", "ka_init", "ka_init_k", "ka_sweep",
     "ka_observe", "ka_run", "ka_get_state", "ka_set_state", "ka_sim_info", "ka_set_option",
     "ka_timing", "ka_sim_path", "ka_free", "ka_last_error",
@@ -78,6 +78,7 @@ def load():
     sig = {
         "ka_graph_lattice": ([I, I, PP], I),
         "ka_graph_rrg": ([I64, I, U64, PP], I),
+        "ka_graph_layered": ([I, I, I, U64, PP], I),
         "ka_graph_from_adjacency": ([I64, I, P, PP], I),
         "ka_graph_info": ([P, P, P, P, P], I),
         "ka_graph_export": ([P, P, P, P, P], I),
@@ -212,6 +213,12 @@ def ka_graph_lattice(d: int, L: int) -> Graph:
 def ka_graph_rrg(N: int, z: int, graph_seed: int) -> Graph:
     h = ctypes.c_void_p()
     _check(load().ka_graph_rrg(N, z, graph_seed, ctypes.byref(h)))
+    return Graph(h)
+
+
+def ka_graph_layered(d: int, L: int, M: int, graph_seed: int) -> Graph:
+    h = ctypes.c_void_p()
+    _check(load().ka_graph_layered(d, L, M, graph_seed, ctypes.byref(h)))
     return Graph(h)
 
 

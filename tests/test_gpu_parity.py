@@ -103,6 +103,24 @@ def test_rrg_parity(oracle, N, z, m, rho, R, path):
     _check_case(oracle, g, og, m, K, 99 + N, R, [1, 3, 5], path)
 
 
+LAYERED_CASES = [
+    # d, L, M, m, rho, R
+    (2, 8, 3, 2, 0.7, 64),
+    (3, 4, 4, 3, 0.8, 128),
+    (2, 6, 2, 1, 0.6, 64),      # L % 4 != 0: greedy classes
+    (3, 8, 2, 3, 0.85, 256),
+]
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("d,L,M,m,rho,R", LAYERED_CASES)
+def test_layered_parity(oracle, d, L, M, m, rho, R, path):
+    g = ka.ka_graph_layered(d, L, M, 5)
+    og = oracle.layered(d, L, M, 5)
+    K = oracle.k_from_rho(og.N, rho)
+    _check_case(oracle, g, og, m, K, 71 + M, R, [1, 2, 3], path)
+
+
 @pytest.mark.parametrize("path", [1, 2])
 def test_degenerate_particle_numbers(oracle, path):
     g = ka.ka_graph_lattice(2, 8)

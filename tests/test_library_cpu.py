@@ -89,3 +89,13 @@ def test_log_time_grid():
     grid = ka.log_time_grid(10_000)
     assert grid[0] == 0 and grid[-1] == 10_000 and len(grid) == 38
     assert grid[:8] == [0, 1, 2, 3, 5, 6, 7, 10]
+
+
+@pytest.mark.parametrize("d,L,M,seed", [(3, 4, 3, 7), (2, 8, 5, 1), (3, 6, 2, 3), (2, 14, 4, 9), (3, 8, 16, 2)])
+def test_layered_graph_matches_oracle(oracle, d, L, M, seed):
+    g = ka.ka_graph_layered(d, L, M, seed)
+    og = oracle.layered(d, L, M, seed)
+    adj, eu, ev, ec = ka.ka_graph_export(g)
+    assert np.array_equal(adj, og.adj)
+    assert np.array_equal(eu, og.eu) and np.array_equal(ev, og.ev) and np.array_equal(ec, og.ecls)
+    assert g.C == og.C

@@ -9,6 +9,9 @@
 - Greedy distance-2 colouring: valid (same check as above) and greedy-minimal (each
   edge's colour is the smallest one not held by a conflicting earlier edge), with the
   conflict sets recomputed here from BFS distances.
+- Layered random graphs (Sec. 5.2): simple, 2d-regular, every link projects onto a lattice
+  bond, one copy is the plain lattice, each bond's links are a uniform permutation of the
+  copies (chi-square), and the projected classes pass the same distance check.
 """
 import itertools
 from collections import Counter
@@ -122,3 +125,62 @@ def test_graph_from_adjacency_rejects_non_simple(oracle):
     adj = np.array([[1, 1], [0, 0], [3, 3], [2, 2]], dtype=np.int32)  # multi-edges
     with pytest.raises(ValueError):
         oracle.graph_from_adjacency(adj)
+
+
+# ------------------------------------------------------------------------ layered graphs (Sec. 5.2)
+@pytest.mark.parametrize("d,L,M", [(2, 4, 3), (2, 8, 2), (3, 4, 2), (2, 6, 3)])
+def test_layered_graph_structure_and_classes(oracle, d, L, M):
+    g = oracle.layered(d, L, M, 11)
+    Nb = L ** d
+    assert g.N == Nb * M and g.z == 2 * d
+    base = oracle.lattice(d, L) if L % 4 == 0 else None
+    for v in range(g.N):
+        row = [int(u) for u in g.adj[v]]
+        assert len(set(row)) == g.z and v not in row
+        for u in row:
+            assert v in g.adj[u]
+        # every link projects onto a lattice bond
+        i = v % Nb
+        proj = sorted(u % Nb for u in row)
+        xs = np.unravel_index(i, (L,) * d, order="F")
+        nbrs = []
+        for mu in range(d):
+            for s in (1, -1):
+                y = list(xs)
+                y[mu] = (y[mu] + s) % L
+                nbrs.append(int(np.ravel_multi_index(y, (L,) * d, order="F")))
+        assert proj == sorted(nbrs)
+    _check_classes_distance2(g)
+    if base is not None:
+        assert g.C == 4 * d
+
+
+def test_layered_single_copy_is_the_lattice(oracle):
+    g = oracle.layered(3, 4, 1, 5)
+    b = oracle.lattice(3, 4)
+    assert np.array_equal(g.adj, np.sort(b.adj, axis=1))
+
+
+def test_layered_permutations_uniform(oracle):
+    """Each bond's links are a uniform random permutation of the copies (M = 3: six
+    permutations, chi-square over all bonds of a 2D L=32 base lattice)."""
+    d, L, M = 2, 32, 3
+    adj = oracle.layered_adjacency(d, L, M, 123)
+    Nb = L * L
+    counts = {}
+    for i in range(Nb):
+        x, y = i % L, i // L
+        j = ((x + 1) % L) + L * y                    # bond (i, i + e_0)
+        perm = []
+        for a in range(M):
+            u = a * Nb + i
+            partner = [int(v) for v in adj[u] if int(v) % Nb == j]
+            assert len(partner) == 1
+            perm.append(partner[0] // Nb)
+        assert sorted(perm) == list(range(M))
+        counts[tuple(perm)] = counts.get(tuple(perm), 0) + 1
+    obs = np.array(list(counts.values()), dtype=float)
+    assert len(obs) == 6
+    exp = Nb / 6
+    chi2 = float(((obs - exp) ** 2 / exp).sum())
+    assert chi2 < 30.0, chi2
