@@ -122,6 +122,18 @@ int ka_sweep(ka_sim *s, int64_t n_sweeps);
 int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
                int64_t *persistence);
 
+/* Spatial four-point sums at the current t on a lattice (Sec. 2.2 g4 and chi4 = sum_r g4;
+ * Sec. 3.3 Phi(r, t) as the popcount of the AND of n_i(t), n_i(0), n_j(t), n_j(0)).  With
+ * q_i^b = n_i^b(t) n_i^b(0), for every shell r2 = |delta|^2 <= r2_max of displacements delta
+ * of the torus (each displacement once, components in the minimum image |c| <= L/2):
+ *   S2[r2]    = sum_i sum_{|delta|^2 = r2} sum_b q_i^b q_{i+delta}^b            (= Phi)
+ *   S11[r2]   = sum_i sum_{|delta|^2 = r2} (sum_b q_i^b) (sum_b q_{i+delta}^b)
+ *   count[r2] = number of displacements in the shell.
+ * Arrays of r2_max + 1 values (any may be NULL); r2_max <= 2048; up to 1024 replicas.
+ * g4(r) = (S2/R - S11/R^2) / (N rho^2 (1-rho)^2) then sums to chi4 over all shells.
+ * KA_EINVAL for general graphs.  Synchronises. */
+int ka_observe_pairs(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *count);
+
 /* Run to each of the n_obs non-decreasing absolute sweep indices obs_times[q] (each >= the
  * current t) and record the counts of ka_observe there into row q of density/overlap/
  * persistence (int64 [n_obs][n_replicas], any may be NULL).  Observations stay on the

@@ -289,3 +289,50 @@ class Sim:
 
     def observe(self):
         return observe(self.occ, self.occ0, self.moved)
+
+
+# ----------------------------------------------------------------------------- spatial pairs
+def displacement_shells(d: int, L: int, r2_max: int):
+    """Every displacement of the periodic lattice once (components taken in the minimum
+    image, |c| <= L/2), with its squared Euclidean norm, for norms <= r2_max."""
+    import itertools
+    out = []
+    for comps in itertools.product(range(L), repeat=d):
+        v = [c if c <= L // 2 else c - L for c in comps]
+        r2 = sum(c * c for c in v)
+        if r2 <= r2_max:
+            out.append((tuple(v), r2))
+    return out
+
+
+def pair_sums(occ: np.ndarray, occ0: np.ndarray, d: int, L: int, r2_max: int):
+    """Four-point sums of Sec. 2.2 / Sec. 3.3 over ordered site pairs (i, i+delta) with
+    |delta|^2 = r2, where q_i^b = n_i^b(t) n_i^b(0):
+        S2[r2]  = sum_i sum_delta sum_b q_i^b q_{i+delta}^b          (Phi(r, t))
+        S11[r2] = sum_i sum_delta (sum_b q_i^b) (sum_b q_{i+delta}^b)
+    and count[r2] = number of displacements in the shell.  Plain numpy rolls."""
+    R = occ.shape[0]
+    shape = (R,) + (L,) * d                      # x fastest -> last axis
+    q = (occ.astype(np.int64) * occ0.astype(np.int64)).reshape(shape)
+    qs = q.sum(axis=0)                           # sum over replicas, per site
+    S2 = np.zeros(r2_max + 1, dtype=np.int64)
+    S11 = np.zeros(r2_max + 1, dtype=np.int64)
+    count = np.zeros(r2_max + 1, dtype=np.int64)
+    for v, r2 in displacement_shells(d, L, r2_max):
+        # site i at coordinates x (axis order reversed: last array axis is x_0)
+        shift = tuple(-c for c in reversed(v))
+        axes = tuple(range(1, d + 1))
+        qj = np.roll(q, shift, axis=axes)        # qj[..., x] = q[..., x + v]
+        S2[r2] += int((q * qj).sum())
+        qsj = np.roll(qs, shift, axis=tuple(range(d)))
+        S11[r2] += int((qs * qsj).sum())
+        count[r2] += 1
+    return S2, S11, count
+
+
+def g4_from_pairs(N: int, K: int, R: int, S2, S11):
+    """g4(r) = sum over pairs at r of the replica covariance of q_i, q_j, divided by
+    N rho^2 (1-rho)^2 (the normalisation under which sum_r g4 = chi4 of Sec. 2.2)."""
+    rho = K / N
+    cov = np.asarray(S2, dtype=np.float64) / R - np.asarray(S11, dtype=np.float64) / (R * R)
+    return cov / (N * rho * rho * (1.0 - rho) ** 2)

@@ -941,6 +941,65 @@ int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out)
   return KA_OK;
 }
 
+extern "C" int ka_observe_pairs(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *count)
+{
+  int rc = check_sim(s);
+  if (rc) return rc;
+  if (!s->lattice) return fail(KA_EINVAL, "spatial pair sums need a lattice");
+  if (r2_max < 0 || r2_max > ka::kMaxPairShells - 1)
+    return fail(KA_EINVAL, "r2_max must be in [0, %d]", ka::kMaxPairShells - 1);
+  if (s->W > 16) return fail(KA_EINVAL, "spatial pair sums support up to 1024 replicas");
+  const int d = s->geom.d, L = s->geom.L;
+  // every displacement of the torus once, components in the minimum image (|c| <= L/2)
+  std::vector<int4> disp;
+  std::vector<int64_t> cnt((size_t)r2_max + 1, 0);
+  const int n_total = d == 2 ? L * L : L * L * L;
+  for (int q = 0; q < n_total; ++q) {
+    int c[3] = {q % L, (q / L) % L, d == 3 ? q / (L * L) : 0};
+    int r2 = 0;
+    for (int k = 0; k < d; ++k) {
+      if (c[k] > L / 2) c[k] -= L;
+      r2 += c[k] * c[k];
+    }
+    if (r2 > r2_max) continue;
+    disp.push_back(make_int4(c[0], c[1], c[2], r2));
+    cnt[(size_t)r2] += 1;
+  }
+  DeviceGuard dg(s->device);
+  int4 *d_disp = nullptr;
+  unsigned long long *d_out = nullptr;
+  const size_t shells = (size_t)r2_max + 1;
+  hipError_t e = dalloc(&d_disp, disp.size() * sizeof(int4));
+  if (e == hipSuccess) e = dalloc(&d_out, 2 * shells * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemcpyAsync(d_disp, disp.data(), disp.size() * sizeof(int4), hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(d_out, 0, 2 * shells * sizeof(unsigned long long), s->stream);
+  if (e == hipSuccess) {
+    ka::PairArgs a{};
+    a.n = s->n;
+    a.n0 = s->n0;
+    a.g = s->geom;
+    a.planes = s->planes;
+    a.disp = d_disp;
+    a.n_disp = (int)disp.size();
+    a.r2_max = r2_max;
+    a.S2 = d_out;
+    a.S11 = d_out + shells;
+    e = ka::launch_pairs(a, s->wpt, s->stream);
+  }
+  std::vector<unsigned long long> host(2 * shells);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), d_out, 2 * shells * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(d_disp);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(e, "ka_observe_pairs");
+  for (size_t q = 0; q < shells; ++q) {
+    if (S2) S2[q] = (int64_t)host[q];
+    if (S11) S11[q] = (int64_t)host[shells + q];
+    if (count) count[q] = cnt[q];
+  }
+  return KA_OK;
+}
+
 extern "C" int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, int64_t *t)
 {
   int rc = check_sim(s);

@@ -114,6 +114,21 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
 hipError_t launch_init(const InitArgs &a, int R, int wpt, hipStream_t s);
 hipError_t launch_observe(const ObserveArgs &a, int wpt, hipStream_t s);
 size_t sweep_lds_bytes(int N, int wpt);
+
+// Spatial four-point sums (ka_pairs.hip).
+constexpr int kMaxPairShells = 2049;   // r2_max <= 2048
+struct PairArgs {
+  const u64 *n;
+  const u64 *n0;
+  LatticeGeom g;
+  int planes;
+  const int4 *disp;                    // (dx, dy, dz, r2)
+  int n_disp;
+  int r2_max;
+  unsigned long long *S2;              // [r2_max + 1]
+  unsigned long long *S11;
+};
+hipError_t launch_pairs(const PairArgs &a, int wpt, hipStream_t s);
 int max_lds_bytes();
 
 }  // namespace ka

@@ -25,7 +25,7 @@ KA_OPT_TIMING = 2
 SYMBOLS = (
     "ka_graph_lattice", "ka_graph_rrg", "ka_graph_layered", "ka_graph_from_adjacency", "ka_graph_info",
     "ka_graph_export", "ka_graph_free", "ka_footprint", "ka_init", "ka_init_k", "ka_sweep",
-    "ka_observe", "ka_run", "ka_get_state", "ka_set_state", "ka_sim_info", "ka_set_option",
+    "ka_observe", "ka_observe_pairs", "ka_run", "ka_get_state", "ka_set_state", "ka_sim_info", "ka_set_option",
     "ka_timing", "ka_sim_path", "ka_free", "ka_last_error",
     "ka_batch_create", "ka_batch_add", "ka_batch_run", "ka_batch_steps_left", "ka_batch_poll",
     "ka_batch_wait_all", "ka_batch_set_option", "ka_batch_info", "ka_batch_free",
@@ -89,6 +89,7 @@ def load():
         "ka_sweep": ([P, I64], I),
         "ka_observe": ([P, P, P, P, P], I),
         "ka_run": ([P, P, I, P, P, P], I),
+        "ka_observe_pairs": ([P, I, P, P, P], I),
         "ka_get_state": ([P, P, P, P, P], I),
         "ka_set_state": ([P, P, P, P, I64], I),
         "ka_sim_info": ([P, P, P, P, P, P, P], I),
@@ -275,6 +276,22 @@ def ka_observe(s: Sim):
     pers = np.empty(s.R, dtype=np.int64)
     _check(load().ka_observe(s.handle, ctypes.byref(t), _ptr(dens), _ptr(ov), _ptr(pers)))
     return t.value, dens, ov, pers
+
+
+def ka_observe_pairs(s: Sim, r2_max: int):
+    """Four-point sums per shell r2 = 0..r2_max: (S2, S11, count), int64 arrays."""
+    S2 = np.empty(r2_max + 1, dtype=np.int64)
+    S11 = np.empty(r2_max + 1, dtype=np.int64)
+    cnt = np.empty(r2_max + 1, dtype=np.int64)
+    _check(load().ka_observe_pairs(s.handle, int(r2_max), _ptr(S2), _ptr(S11), _ptr(cnt)))
+    return S2, S11, cnt
+
+
+def g4_from_pairs(N: int, K: int, R: int, S2, S11):
+    """g4 per shell: (S2/R - S11/R^2) / (N rho^2 (1-rho)^2), rho = K/N (Sec. 2.2)."""
+    rho = K / N
+    cov = np.asarray(S2, dtype=np.float64) / R - np.asarray(S11, dtype=np.float64) / (R * R)
+    return cov / (N * rho * rho * (1.0 - rho) ** 2)
 
 
 def ka_run(s: Sim, obs_times):

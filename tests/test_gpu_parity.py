@@ -200,3 +200,64 @@ def test_replica_subset_independence(oracle):
     ns = ka.ka_get_state(small)[0]
     nb = ka.ka_get_state(big)[0]
     assert np.array_equal(ns[0], nb[0])
+
+
+# ------------------------------------------------------------------------ four-point pair sums
+PAIR_CASES = [
+    # d, L, m, rho, R, sweeps, r2_max
+    (2, 8, 2, 0.7, 64, 3, 32),        # full coverage: 2 * 4^2
+    (2, 12, 1, 0.55, 128, 2, 9),
+    (3, 4, 3, 0.6, 256, 4, 12),       # full coverage: 3 * 2^2
+    (3, 8, 3, 0.8, 192, 2, 6),
+]
+
+
+@pytest.mark.parametrize("d,L,m,rho,R,sweeps,r2_max", PAIR_CASES)
+def test_pair_sums_parity(oracle, d, L, m, rho, R, sweeps, r2_max):
+    g = ka.ka_graph_lattice(d, L)
+    og = oracle.lattice(d, L)
+    K = oracle.k_from_rho(og.N, rho)
+    _say(f"pair sums d={d} L={L} R={R} r2_max={r2_max}")
+    sim = ka.ka_init_k(g, m, K, 13, R)
+    ka.ka_sweep(sim, sweeps)
+    S2, S11, cnt = ka.ka_observe_pairs(sim, r2_max)
+    orc = oracle.Sim(og, m, K, 13, range(R))
+    orc.sweep(sweeps)
+    oS2, oS11, ocnt = oracle.pair_sums(orc.occ, orc.occ0, d, L, r2_max)
+    assert np.array_equal(cnt, ocnt)
+    assert np.array_equal(S2, oS2) and np.array_equal(S11, oS11)
+
+
+def test_pair_sums_cover_chi4_gpu():
+    """All displacements of 3D L=16 x 256 replicas: sum S2 = sum_b overlap_b^2, sum S11 =
+    (sum_b overlap_b)^2, S2[0] = sum_b overlap_b, so sum_r g4(r) = chi4."""
+    g = ka.ka_graph_lattice(3, 16)
+    _say("pair sums full coverage 3D L=16")
+    sim = ka.ka_init(g, 3, 0.75, 5, 256)
+    ka.ka_sweep(sim, 20)
+    S2, S11, cnt = ka.ka_observe_pairs(sim, 3 * 8 * 8)
+    _, dens, ov, pers = ka.ka_observe(sim)
+    assert cnt.sum() == g.N
+    assert S2.sum() == int((ov.astype(object) ** 2).sum())
+    assert S11.sum() == int(ov.sum()) ** 2
+    assert S2[0] == int(ov.sum())
+    g4 = ka.g4_from_pairs(g.N, sim.K, 256, S2, S11)
+    _, chi4, _ = ka.derived_observables(g.N, sim.K, ov, pers)
+    assert abs(g4.sum() - chi4[0]) < 1e-9 * max(1.0, abs(chi4[0]))
+
+
+def test_pair_sums_full_workload_properties():
+    """3D L=128 x 256 replicas (the benchmark workload) out to r = 6 (the paper's range):
+    at t = 0, S2[0] equals the summed overlap K*R, S11[0] = sum_i popcount(n0_i)^2 >= S2[0];
+    after sweeps S2[0] still equals the summed overlap."""
+    g = ka.ka_graph_lattice(3, 128)
+    _say("pair sums 3D L=128 x 256")
+    sim = ka.ka_init(g, 3, 0.85, 1, 256)
+    S2, S11, cnt = ka.ka_observe_pairs(sim, 36)
+    assert S2[0] == sim.K * 256 and S11[0] >= S2[0]
+    assert cnt[1] == 6 and cnt[2] == 12 and cnt[36] > 0
+    ka.ka_sweep(sim, 3)
+    S2, S11, cnt = ka.ka_observe_pairs(sim, 36)
+    _, dens, ov, pers = ka.ka_observe(sim)
+    assert S2[0] == int(ov.sum())
+    assert (S2 >= 0).all() and (S11 >= 0).all()

@@ -308,3 +308,47 @@ def test_every_replica_has_its_own_noise(oracle):
     assert len({row.tobytes() for row in occ}) == 256
     occ0 = oracle.init(g, 20, 42, range(256))
     assert len({row.tobytes() for row in occ0}) == 256
+
+
+# ------------------------------------------------------------------------ four-point sums
+def test_pair_sums_brute_force_tiny(oracle):
+    """S2, S11 against an explicit double loop over site pairs (2D L=4, r2 <= 8)."""
+    g = oracle.lattice(2, 4)
+    s = oracle.Sim(g, 2, 9, 5, range(64))
+    s.sweep(3)
+    S2, S11, count = oracle.pair_sums(s.occ, s.occ0, 2, 4, 8)
+    q = (s.occ.astype(np.int64) * s.occ0)
+    L = 4
+    bS2 = np.zeros(9, dtype=np.int64)
+    bS11 = np.zeros(9, dtype=np.int64)
+    for i in range(16):
+        for j in range(16):
+            dx = abs(i % L - j % L)
+            dy = abs(i // L - j // L)
+            dx, dy = min(dx, L - dx), min(dy, L - dy)
+            r2 = dx * dx + dy * dy
+            if r2 <= 8:
+                bS2[r2] += int((q[:, i] * q[:, j]).sum())
+                bS11[r2] += int(q[:, i].sum() * q[:, j].sum())
+    assert np.array_equal(S2, bS2) and np.array_equal(S11, bS11)
+    assert count.sum() == 16 and count[0] == 1 and count[1] == 4
+
+
+@pytest.mark.parametrize("d,L", [(2, 8), (3, 4)])
+def test_pair_sums_cover_chi4(oracle, d, L):
+    """Summed over every displacement: sum S2 = sum_b overlap_b^2, sum S11 =
+    (sum_b overlap_b)^2, S2[0] = sum_b overlap_b; hence sum_r g4(r) = chi4."""
+    g = oracle.lattice(d, L)
+    K = oracle.k_from_rho(g.N, 0.6)
+    s = oracle.Sim(g, g.z // 2, K, 7, range(128))
+    s.sweep(4)
+    _, ov, pers = s.observe()
+    r2_all = d * (L // 2) ** 2
+    S2, S11, count = oracle.pair_sums(s.occ, s.occ0, d, L, r2_all)
+    assert count.sum() == g.N
+    assert S2.sum() == int((ov.astype(np.int64) ** 2).sum())
+    assert S11.sum() == int(ov.sum()) ** 2
+    assert S2[0] == int(ov.sum())
+    g4 = oracle.g4_from_pairs(g.N, K, 128, S2, S11)
+    _, chi4, _ = oracle.derived(g.N, K, ov, pers)
+    assert abs(g4.sum() - chi4) < 1e-9 * max(1.0, abs(chi4))
