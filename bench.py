@@ -50,9 +50,11 @@ def log(msg):
 def class_pass_bytes(w, N, W):
     """Algorithmic HBM bytes of one global class pass over all words (per-pass model):
     every site's words are read once as endpoint or neighbour (8 B), the endpoints (half of
-    the sites) are written (8 B) and their moved-ever words read and written (16 B)."""
+    the sites) are written (8 B) and their moved-ever words read (8 B).  A moved-ever word
+    is written only when it gains a bit (at most 64 times per word over a whole run), which
+    the model leaves out."""
     if w["kind"] == "lattice":
-        return N * W * 8 + (N // 2) * W * 8 + (N // 2) * W * 16
+        return N * W * 8 + (N // 2) * W * 8 + (N // 2) * W * 8
     return None
 
 
@@ -128,7 +130,7 @@ def graph_bytes_model(adj, eu, ev, ec, C, z, W):
         touched[ev[sel]] = True
         touched[adj[eu[sel]].ravel()] = True
         touched[adj[ev[sel]].ravel()] = True
-        total += int(touched.sum()) * 8 * W + Ec * (16 + 2 * 4 * z + 2 * 8 * W + 2 * 16 * W)
+        total += int(touched.sum()) * 8 * W + Ec * (16 + 2 * 4 * z + 2 * 8 * W + 2 * 8 * W)
     return total
 
 
@@ -152,7 +154,7 @@ def run_batch_workload(args):
             continue
         if inst["kind"] == "lattice":
             graphs[key] = ka.ka_graph_lattice(inst["d"], inst["L"])
-            bytes_per_sweep[key] = 20 * inst["N"] * (inst["R"] // 64) * 4 * inst["d"]
+            bytes_per_sweep[key] = 16 * inst["N"] * (inst["R"] // 64) * 4 * inst["d"]
         else:
             g = ka.ka_graph_rrg(inst["N"], inst["z"], inst["graph_seed"])
             graphs[key] = g

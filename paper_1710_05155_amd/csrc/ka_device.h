@@ -335,15 +335,20 @@ __device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom
   if (any) {
     st<WPT>(nb, si.idx, ni);
     st<WPT>(nb, sj.idx, nj);
+    // f only gains a bit the first time a site changes in a replica, so it is stored
+    // only then: over a run a word is rewritten at most 64 times.
     Elem<WPT> fi = ld<WPT>(fb, si.idx);
     Elem<WPT> fj = ld<WPT>(fb, sj.idx);
+    u64 new_i = 0, new_j = 0;
 #pragma unroll
     for (int w = 0; w < WPT; ++w) {
+      new_i |= d[w] & ~fi.w[w];
+      new_j |= d[w] & ~fj.w[w];
       fi.w[w] |= d[w];
       fj.w[w] |= d[w];
     }
-    st<WPT>(fb, si.idx, fi);
-    st<WPT>(fb, sj.idx, fj);
+    if (new_i) st<WPT>(fb, si.idx, fi);
+    if (new_j) st<WPT>(fb, sj.idx, fj);
   }
 }
 
@@ -398,13 +403,16 @@ __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int32_t *adj,
     st<WPT>(nb, v, nj);
     Elem<WPT> fu = ld<WPT>(fb, u);
     Elem<WPT> fv = ld<WPT>(fb, v);
+    u64 new_u = 0, new_v = 0;
 #pragma unroll
     for (int w = 0; w < WPT; ++w) {
+      new_u |= d[w] & ~fu.w[w];
+      new_v |= d[w] & ~fv.w[w];
       fu.w[w] |= d[w];
       fv.w[w] |= d[w];
     }
-    st<WPT>(fb, u, fu);
-    st<WPT>(fb, v, fv);
+    if (new_u) st<WPT>(fb, u, fu);
+    if (new_v) st<WPT>(fb, v, fv);
   }
 }
 
