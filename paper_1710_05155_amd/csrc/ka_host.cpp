@@ -462,6 +462,7 @@ void free_device(ka_sim *s)
   (void)hipFree(s->adj);
   (void)hipFree(s->edges);
   (void)hipFree(s->class_start_d);
+  (void)hipFree(s->site_of);
   (void)hipFree(s->thr_u);
   (void)hipFree(s->thr_i);
   (void)hipFree(s->err);
@@ -769,18 +770,56 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
     s->geom.N = (int)g->N;
     lattice_class_tables(g->d, s->lcls);
   } else {
-    // class-sorted edge records (u, v, e, 0), edges of one class in increasing e
+    // Device numbering of the vertices: breadth-first order, so the neighbours of vertices
+    // with nearby numbers have nearby numbers and gathers share cache lines.
+    const int64_t Nv = g->N;
+    const int z = g->z;
+    s->label.assign((size_t)Nv, -1);
+    std::vector<int32_t> site_of((size_t)Nv);
+    int64_t next = 0;
+    for (int64_t root = 0; root < Nv; ++root) {
+      if (s->label[(size_t)root] >= 0) continue;
+      int64_t head = next;
+      s->label[(size_t)root] = (int32_t)next;
+      site_of[(size_t)next++] = (int32_t)root;
+      while (head < next) {
+        const int32_t v = site_of[(size_t)head++];
+        for (int k = 0; k < z; ++k) {
+          const int32_t w = g->adj[(size_t)v * z + k];
+          if (s->label[(size_t)w] < 0) {
+            s->label[(size_t)w] = (int32_t)next;
+            site_of[(size_t)next++] = w;
+          }
+        }
+      }
+    }
+    std::vector<int32_t> adj_dev((size_t)Nv * z);
+    for (int64_t v = 0; v < Nv; ++v)
+      for (int k = 0; k < z; ++k)
+        adj_dev[(size_t)s->label[(size_t)v] * z + k] = s->label[(size_t)g->adj[(size_t)v * z + k]];
+    // class-sorted edge records (u, v, e, 0) in device numbering, canonical edge id e;
+    // inside a class ordered by the smaller endpoint (any order gives the same result)
     const int64_t E = (int64_t)g->eu.size();
     s->class_start.assign((size_t)g->C + 1, 0);
     for (int64_t q = 0; q < E; ++q) s->class_start[(size_t)g->ecls[q] + 1]++;
     for (int c = 0; c < g->C; ++c) s->class_start[(size_t)c + 1] += s->class_start[(size_t)c];
     std::vector<int> fill(s->class_start.begin(), s->class_start.end() - 1);
     std::vector<int4> rec((size_t)E);
-    for (int64_t q = 0; q < E; ++q) rec[(size_t)fill[(size_t)g->ecls[q]]++] = make_int4(g->eu[q], g->ev[q], (int)q, 0);
+    for (int64_t q = 0; q < E; ++q)
+      rec[(size_t)fill[(size_t)g->ecls[q]]++] =
+          make_int4(s->label[(size_t)g->eu[q]], s->label[(size_t)g->ev[q]], (int)q, 0);
+    for (int c = 0; c < g->C; ++c)
+      std::sort(rec.begin() + s->class_start[(size_t)c], rec.begin() + s->class_start[(size_t)c + 1],
+                [](const int4 &x, const int4 &y) {
+                  const int kx = std::min(x.x, x.y), ky = std::min(y.x, y.y);
+                  return kx != ky ? kx < ky : x.z < y.z;
+                });
     e = dalloc(&s->adj, g->adj.size() * 4);
+    if (e == hipSuccess) e = dalloc(&s->site_of, site_of.size() * sizeof(int32_t));
+    if (e == hipSuccess) e = hipMemcpy(s->site_of, site_of.data(), site_of.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&s->edges, rec.size() * sizeof(int4));
     if (e == hipSuccess) e = dalloc(&s->class_start_d, s->class_start.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMemcpy(s->adj, g->adj.data(), g->adj.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(s->adj, adj_dev.data(), adj_dev.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(s->class_start_d, s->class_start.data(), s->class_start.size() * sizeof(int), hipMemcpyHostToDevice);
@@ -808,6 +847,7 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
   a.planes = s->planes;
   a.is_lattice = s->lattice;
   a.g = s->geom;
+  a.site_of = s->site_of;
   e = hipMemsetAsync(s->err, 0, sizeof(int), s->stream);
   if (e == hipSuccess) e = ka::launch_init(a, s->R, s->wpt, s->stream);
   if (e != hipSuccess) {
@@ -1018,7 +1058,7 @@ extern "C" int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, i
     e = hipMemcpy(buf.data(), srcs[k], words * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "ka_get_state copy");
     for (int64_t i = 0; i < s->N; ++i) {
-      const int64_t el = s->lattice ? lattice_element(s->geom, i) : i;
+      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->label[(size_t)i];
       for (int p = 0; p < s->planes; ++p)
         for (int w = 0; w < s->wpt; ++w)
           outs[k][(size_t)(p * s->wpt + w) * s->N + i] = buf[((size_t)p * s->N + el) * s->wpt + w];
@@ -1044,7 +1084,7 @@ extern "C" int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, co
   if (e != hipSuccess) return hip_fail(e, "ka_set_state");
   for (int k = 0; k < 3; ++k) {
     for (int64_t i = 0; i < s->N; ++i) {
-      const int64_t el = s->lattice ? lattice_element(s->geom, i) : i;
+      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->label[(size_t)i];
       for (int p = 0; p < s->planes; ++p)
         for (int w = 0; w < s->wpt; ++w)
           buf[((size_t)p * s->N + el) * s->wpt + w] = ins[k][(size_t)(p * s->wpt + w) * s->N + i];

@@ -13,7 +13,9 @@ typedef unsigned long long u64;
 // their block coordinates p_nu = x_nu / 4 (pos = sum_nu p_nu Q^nu, Q = L/4).  Element index
 // = sub * P + pos with P = Q^d.  Every edge class is a union of whole sublattices (its lower
 // endpoints), so one pass writes exactly half of the sublattices and threads that walk pos
-// read and write consecutive addresses.  General graphs use the vertex id as index.
+// read and write consecutive addresses.  General graphs number vertices in breadth-first
+// order (neighbours of nearby vertices land near each other); random counters and initial
+// keys keep the canonical edge and vertex ids.
 // An element holds wpt consecutive 64-bit words (wpt = 2 when the replica count is a
 // multiple of 128: word pair p = words 2p, 2p+1; else 1); plane p covers words
 // p*wpt .. p*wpt+wpt-1.
@@ -94,6 +96,7 @@ struct InitArgs {
   int planes;
   int is_lattice;
   LatticeGeom g;
+  const int32_t *site_of;   // general graphs: canonical vertex of each device index
 };
 
 struct ObserveArgs {

@@ -28,6 +28,7 @@ struct ka_sim {
   ka::LatticeGeom geom{};
   ka::LatticeClasses lcls{};
   std::vector<int> class_start;   // general graphs: [C+1]
+  std::vector<int32_t> label;     // general graphs: device index of canonical vertex i
   // parameters
   int m = 0;
   int64_t K = 0;
@@ -42,6 +43,7 @@ struct ka_sim {
   int32_t *adj = nullptr;
   int4 *edges = nullptr;
   int *class_start_d = nullptr;
+  int32_t *site_of = nullptr;     // general graphs: canonical vertex of device index
   ka::u64 *thr_u = nullptr;
   long long *thr_i = nullptr;
   int *err = nullptr;

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(kSelBlock) void k_init_select(InitArgs a)
 // Element index -> canonical site id.
 __device__ __forceinline__ int element_site(const InitArgs &a, int idx)
 {
-  if (!a.is_lattice) return idx;
+  if (!a.is_lattice) return a.site_of[idx];
   const int sub = idx / a.g.P;
   const int pos = idx - sub * a.g.P;
   const Site s = decode(a.g, a.g.d, sub, pos);
