@@ -10,9 +10,11 @@ timed region.
 
 Metric: site-replica move attempts per second = N * R * sweeps * steps / wall time (one
 sweep attempts every edge once per replica, N attempts per replica in the paper's time
-unit).  Also reported: the roofline of the dominant kernel (the global-memory class pass),
-from HIP-event durations of sampled launches inside the timed region, and the oracle's rate
-on a bounded sample on this host's cores.
+unit).  Also reported: the rate without the observations, and the roofline of the dominant
+kernel (the global-memory class pass).  Its average launch time is the HIP-event stream time
+of the timed jobs' sweep loops, less the same number of observations timed on their own,
+divided by the number of class-pass launches; so it includes the short gaps between
+back-to-back launches.  Last, the oracle's rate on a bounded sample on this host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload cubic128]
 """
@@ -116,9 +118,9 @@ def cpu_baseline(w, seconds_target=15.0):
 def graph_bytes_model(adj, eu, ev, ec, C, z, W):
     """Algorithmic bytes of one sweep over a general graph, summed over its class passes:
     per class, the distinct sites read (endpoints and their neighbours, at most N) x 8 B per
-    word, the class records (16 B per edge), the two adjacency rows per edge (4z B each),
+    word, the class records (16 B per edge), the neighbour lists (2(z-1) x 4 B per edge),
     the endpoint words written (2 x 8 B per edge and word) and their moved-ever words read
-    and written (2 x 16 B per edge and word)."""
+    (2 x 8 B per edge and word; as for lattices, the rare moved-ever stores are left out)."""
     import numpy as np
     N = adj.shape[0]
     total = 0
@@ -130,7 +132,7 @@ def graph_bytes_model(adj, eu, ev, ec, C, z, W):
         touched[ev[sel]] = True
         touched[adj[eu[sel]].ravel()] = True
         touched[adj[ev[sel]].ravel()] = True
-        total += int(touched.sum()) * 8 * W + Ec * (16 + 2 * 4 * z + 2 * 8 * W + 2 * 8 * W)
+        total += int(touched.sum()) * 8 * W + Ec * (16 + 2 * 4 * (z - 1) + 2 * 8 * W + 2 * 8 * W)
     return total
 
 
@@ -361,8 +363,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cubic128", choices=sorted(WORKLOADS) + ["batch256", "serve"])
-    ap.add_argument("--timing-every", type=int, default=64,
-                    help="bracket every k-th class-pass launch with HIP events")
+    ap.add_argument("--timing-every", type=int, default=0,
+                    help="also bracket every k-th class-pass launch with HIP events (each bracket adds "
+                         "the events' own stream time to that launch)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sweeps", type=int, default=None,
                     help="override the sweeps per job (profiling runs only; the default is the workload's)")
@@ -416,13 +419,20 @@ def main():
     pass_ms_total = 0.0
     pass_timed = 0
     pass_launches = 0
+    run_events = []
 
-    def job(step_idx):
+    def job(step_idx, timed):
         rho = w["rhos"][step_idx % len(w["rhos"])]
         sim = ka.ka_init(g, w["m"], rho, 1, R, stream=stream)
         if args.timing_every > 0:
             ka.ka_set_option(sim, ka.KA_OPT_TIMING, args.timing_every)
+        if timed:
+            evs = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            evs[0].record(stream)
         dens, ov, pers = ka.ka_run(sim, grid)
+        if timed:
+            evs[1].record(stream)
+            run_events.append(evs)
         K = sim.K
         assert (dens == K).all(), "particle number not conserved"
         C, chi4, P = ka.derived_observables(N, K, ov, pers)
@@ -432,7 +442,7 @@ def main():
         return rho, C, chi4, P, stats, path
 
     for k in range(args.warmup):
-        rho, C, chi4, P, _, _ = job(k)
+        rho, C, chi4, P, _, _ = job(k, False)
         log(f"warmup {k}: rho={rho} C(t_max)={C[-1]:.4f} P(t_max)={P[-1]:.4f}")
 
     torch.cuda.synchronize()
@@ -442,16 +452,31 @@ def main():
     ev0.record(stream)
     path = None
     for k in range(args.steps):
-        rho, C, chi4, P, (launches, timed, ms), path = job(args.warmup + k)
+        rho, C, chi4, P, (launches, timed, ms), path = job(args.warmup + k, True)
         pass_launches += launches
         pass_timed += timed
         pass_ms_total += ms
         log(f"step {k}: rho={rho} C(t_max)={C[-1]:.4f} chi4_max={max(chi4[1:]):.3f} P(t_max)={P[-1]:.4f} "
-            f"passes={launches} timed={timed}")
+            f"passes={launches}")
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = ev0.elapsed_time(ev1)
+    run_ms = sum(a.elapsed_time(b) for a, b in run_events)
+
+    # Observation cost on its own: the same number of observations of a fresh state with no
+    # sweeps in between, timed the same way.  Subtracted from the sweep loops' stream time
+    # it leaves the time of the class passes (kernels and the gaps between them).
+    sim = ka.ka_init(g, w["m"], w["rhos"][0], 1, R, stream=stream)
+    torch.cuda.synchronize()
+    oa, ob = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    oa.record(stream)
+    ka.ka_run(sim, [0] * len(grid))
+    ob.record(stream)
+    torch.cuda.synchronize()
+    obs_ms = oa.elapsed_time(ob)
+    sim.free()
+    sweep_ms = run_ms - args.steps * obs_ms
 
     attempts = N * R * sweeps * args.steps
     value = attempts / wall
@@ -473,10 +498,17 @@ def main():
                    "observations_per_step": len(grid), "path": {1: "global class passes", 2: "LDS-resident"}[path]},
         "edge_replica_updates_per_s": edges * R * sweeps * args.steps / wall,
         "stream_event_ms": gpu_ms,
+        "rate_excluding_observe": attempts / (sweep_ms / 1000.0) if path == 1 else None,
+        "observe_ms_per_step": obs_ms,
     }
     B = class_pass_bytes(w, N, W)
-    if path == 1 and pass_timed > 0 and B:
-        avg_s = pass_ms_total / pass_timed / 1000.0
+    kernel = "k_pass_lattice"
+    if w["kind"] != "lattice":
+        adj, eu, ev, ec = ka.ka_graph_export(g)
+        B = graph_bytes_model(adj, eu, ev, ec, g.C, g.z, W) / g.C
+        kernel = "k_pass_graph"
+    if path == 1 and pass_launches > 0 and B:
+        avg_s = sweep_ms / pass_launches / 1000.0
         achieved = B / avg_s / 1e9
         csrc = os.path.join(ROOT, "paper_1710_05155_amd", "csrc")
         traffic = None
@@ -485,8 +517,9 @@ def main():
                                        os.path.join(ROOT, "profiles", "k_pass_lattice_cubic128.counters.txt"))
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                              "kernel": "k_pass_lattice", "avg_launch_us": avg_s * 1e6,
-                              "bytes_per_launch": B, "timed_launches": pass_timed}
+                              "kernel": kernel, "avg_launch_us": avg_s * 1e6,
+                              "bytes_per_launch": B, "launches": pass_launches,
+                              "sampled_launch_us": pass_ms_total / pass_timed * 1000.0 if pass_timed else None}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w)

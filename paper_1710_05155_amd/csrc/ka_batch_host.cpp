@@ -400,8 +400,9 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
   ka::BatchMember m{};
   m.n = s->n;
   m.f = s->f;
-  m.adj = s->adj;
   m.edges = s->edges;
+  m.nbr = s->nbr;
+  m.stride = (long long)s->edges_total;
   m.class_start = s->class_start_d;
   m.kind = s->lattice ? 0 : 1;
   m.d = s->geom.d;

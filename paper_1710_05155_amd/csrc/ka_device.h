@@ -112,8 +112,12 @@ __device__ __forceinline__ void full_add(u64 a, u64 b, u64 c, u64 &s, u64 &carry
 template <int K>
 __device__ __forceinline__ void bitsum(const u64 (&x)[K], u64 &s0, u64 &s1, u64 &s2)
 {
-  static_assert(K >= 3 && K <= 7, "bit-sliced sum supports 3..7 inputs");
-  if constexpr (K == 3) {
+  static_assert(K >= 2 && K <= 7, "bit-sliced sum supports 2..7 inputs");
+  if constexpr (K == 2) {
+    s0 = x[0] ^ x[1];
+    s1 = x[0] & x[1];
+    s2 = 0;
+  } else if constexpr (K == 3) {
     full_add(x[0], x[1], x[2], s0, s1);
     s2 = 0;
   } else if constexpr (K == 4) {
@@ -352,49 +356,36 @@ __device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom
   }
 }
 
-// One general-graph edge (u, v, e).  The 2z neighbour words are gathered; the partner's
-// word is picked out of the other endpoint's row and zeroed there, so the bit-sliced sum
-// over z inputs counts exactly the z-1 neighbours other than the partner.
+// One general-graph edge: entry k of the class-sorted edge list, record (u, v, e, 0) and
+// its neighbour lists in slot-major arrays of stride `stride`: slots 0..z-2 hold the
+// neighbours of u other than v, slots z-1..2z-3 those of v other than u.  All 2z state
+// words are gathered at once, with no dependent adjacency-row load in front of them.
 template <int Z, int WPT>
-__device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int32_t *adj, int4 E,
-                                           int plane, int m, uint32_t t, uint32_t c,
-                                           uint32_t k0, uint32_t k1)
+__device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int4 *edges, const int32_t *nbr,
+                                           size_t stride, int k, int plane, int m, uint32_t t,
+                                           uint32_t c, uint32_t k0, uint32_t k1)
 {
+  constexpr int K = Z - 1;
+  const int4 E = edges[k];
+  int iu[K], iv[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    iu[q] = nbr[(size_t)q * stride + (size_t)k];
+    iv[q] = nbr[(size_t)(K + q) * stride + (size_t)k];
+  }
   const int u = E.x, v = E.y;
-  int nu[Z], nv[Z];
+  Elem<WPT> ni = ld<WPT>(nb, u);
+  Elem<WPT> nj = ld<WPT>(nb, v);
+  Elem<WPT> xu[K], xv[K];
 #pragma unroll
-  for (int q = 0; q < Z; ++q) {
-    nu[q] = adj[(size_t)u * Z + q];
-    nv[q] = adj[(size_t)v * Z + q];
-  }
-  Elem<WPT> xu[Z], xv[Z];
-#pragma unroll
-  for (int q = 0; q < Z; ++q) {
-    xu[q] = ld<WPT>(nb, nu[q]);
-    xv[q] = ld<WPT>(nb, nv[q]);
-  }
-  Elem<WPT> ni, nj;
-#pragma unroll
-  for (int w = 0; w < WPT; ++w) {
-    ni.w[w] = 0;
-    nj.w[w] = 0;
-  }
-#pragma unroll
-  for (int q = 0; q < Z; ++q) {
-    const bool is_v = nu[q] == v;
-    const bool is_u = nv[q] == u;
-#pragma unroll
-    for (int w = 0; w < WPT; ++w) {
-      nj.w[w] |= is_v ? xu[q].w[w] : 0ull;
-      xu[q].w[w] = is_v ? 0ull : xu[q].w[w];
-      ni.w[w] |= is_u ? xv[q].w[w] : 0ull;
-      xv[q].w[w] = is_u ? 0ull : xv[q].w[w];
-    }
+  for (int q = 0; q < K; ++q) {
+    xu[q] = ld<WPT>(nb, iu[q]);
+    xv[q] = ld<WPT>(nb, iv[q]);
   }
   u64 r[WPT];
   accept_words<WPT>(t, c, (uint32_t)E.z, plane, k0, k1, r);
   u64 d[WPT];
-  exchange<Z, WPT>(ni, nj, xu, xv, r, m, d);
+  exchange<K, WPT>(ni, nj, xu, xv, r, m, d);
   u64 any = 0;
 #pragma unroll
   for (int w = 0; w < WPT; ++w) any |= d[w];

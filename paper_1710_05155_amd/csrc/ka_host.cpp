@@ -451,7 +451,9 @@ size_t state_bytes(int64_t N, int R) { return (size_t)3 * (size_t)N * (size_t)(R
 size_t graph_device_bytes(const ka_graph *g)
 {
   if (g->lattice) return 0;
-  return g->adj.size() * 4u + g->eu.size() * sizeof(int4) + (size_t)(g->C + 1) * sizeof(int);
+  // edge records, slot-major neighbour lists, class offsets, vertex numbering
+  return g->eu.size() * (sizeof(int4) + (size_t)2 * (size_t)(g->z - 1) * 4u) +
+         (size_t)(g->C + 1) * sizeof(int) + (size_t)g->N * 4u;
 }
 
 void free_device(ka_sim *s)
@@ -459,7 +461,7 @@ void free_device(ka_sim *s)
   (void)hipFree(s->n);
   (void)hipFree(s->n0);
   (void)hipFree(s->f);
-  (void)hipFree(s->adj);
+  (void)hipFree(s->nbr);
   (void)hipFree(s->edges);
   (void)hipFree(s->class_start_d);
   (void)hipFree(s->site_of);
@@ -588,8 +590,10 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t)
     ka::PassGraph a{};
     a.n = s->n;
     a.f = s->f;
-    a.adj = s->adj;
-    a.edges = s->edges + s->class_start[c];
+    a.edges = s->edges;
+    a.nbr = s->nbr;
+    a.stride = s->edges_total;
+    a.first = s->class_start[c];
     a.count = s->class_start[c + 1] - s->class_start[c];
     a.N = (int)s->N;
     a.planes = s->planes;
@@ -642,8 +646,9 @@ hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
   a.n0 = s->n0;
   a.g = s->geom;
   a.cls = s->lcls;
-  a.adj = s->adj;
   a.edges = s->edges;
+  a.nbr = s->nbr;
+  a.stride = s->edges_total;
   a.class_start = s->class_start_d;
   a.N = (int)s->N;
   a.C = s->C;
@@ -793,10 +798,6 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
         }
       }
     }
-    std::vector<int32_t> adj_dev((size_t)Nv * z);
-    for (int64_t v = 0; v < Nv; ++v)
-      for (int k = 0; k < z; ++k)
-        adj_dev[(size_t)s->label[(size_t)v] * z + k] = s->label[(size_t)g->adj[(size_t)v * z + k]];
     // class-sorted edge records (u, v, e, 0) in device numbering, canonical edge id e;
     // inside a class ordered by the smaller endpoint (any order gives the same result)
     const int64_t E = (int64_t)g->eu.size();
@@ -814,12 +815,29 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
                   const int kx = std::min(x.x, x.y), ky = std::min(y.x, y.y);
                   return kx != ky ? kx < ky : x.z < y.z;
                 });
-    e = dalloc(&s->adj, g->adj.size() * 4);
+    // Neighbour lists of every record, slot-major: slot q < z-1 is the q-th neighbour of u
+    // other than v, slot z-1+q the q-th neighbour of v other than u (device numbering).
+    const int K = z - 1;
+    std::vector<int32_t> nbr((size_t)2 * K * (size_t)E);
+    for (int64_t k = 0; k < E; ++k) {
+      const int32_t ends[2] = {rec[(size_t)k].x, rec[(size_t)k].y};
+      for (int side = 0; side < 2; ++side) {
+        const int32_t a_end = site_of[(size_t)ends[side]], b_end = site_of[(size_t)ends[1 - side]];
+        int q = 0;
+        for (int j = 0; j < z; ++j) {
+          const int32_t w = g->adj[(size_t)a_end * z + j];
+          if (w == b_end) continue;
+          nbr[(size_t)(side * K + q++) * (size_t)E + (size_t)k] = s->label[(size_t)w];
+        }
+      }
+    }
+    s->edges_total = (size_t)E;
+    e = dalloc(&s->nbr, nbr.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(s->nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&s->site_of, site_of.size() * sizeof(int32_t));
     if (e == hipSuccess) e = hipMemcpy(s->site_of, site_of.data(), site_of.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&s->edges, rec.size() * sizeof(int4));
     if (e == hipSuccess) e = dalloc(&s->class_start_d, s->class_start.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMemcpy(s->adj, adj_dev.data(), adj_dev.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice);
     if (e == hipSuccess)
       e = hipMemcpy(s->class_start_d, s->class_start.data(), s->class_start.size() * sizeof(int), hipMemcpyHostToDevice);

@@ -49,8 +49,10 @@ struct PassLattice {
 struct PassGraph {
   u64 *n;
   u64 *f;
-  const int32_t *adj;        // [N][z]
-  const int4 *edges;         // class slice: (u, v, e, 0)
+  const int4 *edges;         // all edges sorted by class: (u, v, e, 0)
+  const int32_t *nbr;        // [2(z-1)][E] neighbour lists of the records above
+  size_t stride;             // E
+  int first;                 // first edge of the class
   int count;                 // edges in the class
   int N;
   int planes;
@@ -67,8 +69,9 @@ struct SweepLds {
   LatticeGeom g;
   LatticeClasses cls;
   // graph
-  const int32_t *adj;
-  const int4 *edges;         // all edges sorted by (class, e)
+  const int4 *edges;         // all edges sorted by class
+  const int32_t *nbr;        // [2(z-1)][E]
+  size_t stride;             // E
   const int *class_start;    // [C+1]
   int N;
   int C;
@@ -148,8 +151,9 @@ constexpr int kBatchMaxMembers = 1024;
 struct BatchMember {
   u64 *n;
   u64 *f;
-  const int32_t *adj;          // graphs: [N][z]
   const int4 *edges;           // graphs: class-sorted (u, v, e, 0)
+  const int32_t *nbr;          // graphs: [2(z-1)][E] neighbour lists
+  long long stride;            // graphs: E
   const int *class_start;      // graphs: [C+1]
   int kind;                    // 0 lattice, 1 graph
   int d, L, Q, P, N;           // lattice geometry (N for both)

@@ -138,7 +138,8 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_graph(SweepLds a, int m
     for (int c = 0; c < a.C; ++c) {
       const int b0 = a.class_start[c], b1 = a.class_start[c + 1];
       for (int k = b0 + (int)threadIdx.x; k < b1; k += (int)blockDim.x)
-        graph_edge<Z, WPT>(sn, sf, a.adj, a.edges[k], plane, m, t, (uint32_t)c, a.key0, a.key1);
+        graph_edge<Z, WPT>(sn, sf, a.edges, a.nbr, a.stride, k, plane, m, t, (uint32_t)c, a.key0,
+                           a.key1);
       __syncthreads();
     }
     lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)t + 1, cnt);

@@ -40,7 +40,8 @@ struct ka_sim {
   bool own_stream = false;
   // device memory
   ka::u64 *n = nullptr, *n0 = nullptr, *f = nullptr;
-  int32_t *adj = nullptr;
+  int32_t *nbr = nullptr;             // graphs: [2(z-1)][E] neighbour lists of the records
+  size_t edges_total = 0;             // graphs: E
   int4 *edges = nullptr;
   int *class_start_d = nullptr;
   int32_t *site_of = nullptr;     // general graphs: canonical vertex of device index

@@ -45,8 +45,8 @@ __global__ __launch_bounds__(kPassBlock) void k_pass_graph(PassGraph a, int m)
   const int k = blk * kPassBlock + (int)threadIdx.x;
   if (k >= a.count) return;
   const size_t off = (size_t)plane * (size_t)a.N * WPT;
-  graph_edge<Z, WPT>(a.n + off, a.f + off, a.adj, a.edges[k], plane, m, a.t, a.c, a.key0,
-                     a.key1);
+  graph_edge<Z, WPT>(a.n + off, a.f + off, a.edges, a.nbr, a.stride, a.first + k, plane, m, a.t,
+                     a.c, a.key0, a.key1);
 }
 
 template <int WPT>
