@@ -103,7 +103,10 @@ int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_bytes);
  * current HIP device with activation number m (0 <= m <= z-1) and K = floor(rho*N + 1/2)
  * particles (rho in [0, 1], evaluated in IEEE double), and launch the initial-state
  * kernels on hip_stream (a hipStream_t; NULL = a stream the library creates and owns).
- * Returns once the kernels are enqueued; t = 0. */
+ * Returns once the kernels are enqueued; t = 0.  For a general graph the first ka_init
+ * builds the device schedule (vertex numbering, class-sorted edges, neighbour lists) and
+ * keeps a host copy in the graph, so later ka_init calls on it only upload it; the graph
+ * may be freed while sims built from it still run.  Thread-safe on a shared graph. */
 int ka_init(const ka_graph *g, int m, double rho, uint64_t seed, int n_replicas,
             void *hip_stream, ka_sim **out);
 

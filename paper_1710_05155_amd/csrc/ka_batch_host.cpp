@@ -422,7 +422,7 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
   m.s_end = b->step + (int64_t)s->C * n_sweeps;
   b->class_sizes[(size_t)k].clear();
   if (!s->lattice)
-    for (int c = 0; c < s->C; ++c) b->class_sizes[(size_t)k].push_back(s->class_start[(size_t)c + 1] - s->class_start[(size_t)c]);
+    for (int c = 0; c < s->C; ++c) b->class_sizes[(size_t)k].push_back(s->plan->class_start[(size_t)c + 1] - s->plan->class_start[(size_t)c]);
   b->host_tab[k] = m;
   b->sims[(size_t)k] = s;
   b->sweeps[(size_t)k] = n_sweeps;

@@ -9,6 +9,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -593,11 +595,10 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t)
     a.edges = s->edges;
     a.nbr = s->nbr;
     a.stride = s->edges_total;
-    a.first = s->class_start[c];
-    a.count = s->class_start[c + 1] - s->class_start[c];
+    a.first = s->plan->class_start[c];
+    a.count = s->plan->class_start[c + 1] - s->plan->class_start[c];
     a.N = (int)s->N;
-    a.planes = s->planes;
-    a.blocks_per_plane = (a.count + 255) / 256;
+    a.planes = s->planes;   // the launcher picks the workgroup size and blocks per plane
     a.t = t;
     a.c = (uint32_t)c;
     a.key0 = k0;
@@ -700,6 +701,83 @@ int check_init_flag(ka_sim *s)
   return KA_OK;
 }
 
+// The device schedule of a general graph (see GraphPlan), built on first use and kept in the
+// graph: later ka_init calls on the same graph only copy it to the device.  Returns null if
+// host memory runs out.
+std::shared_ptr<const GraphPlan> graph_plan(const ka_graph *g)
+{
+  std::lock_guard<std::mutex> lock(g->plan_mu);
+  if (g->plan) return g->plan;
+  try {
+    auto p = std::make_shared<GraphPlan>();
+    // Device numbering of the vertices: breadth-first order, so the neighbours of vertices
+    // with nearby numbers have nearby numbers and gathers share cache lines.
+    const int64_t Nv = g->N;
+    const int z = g->z;
+    std::vector<int32_t> &label = p->label;
+    std::vector<int32_t> &site_of = p->site_of;
+    label.assign((size_t)Nv, -1);
+    site_of.resize((size_t)Nv);
+    int64_t next = 0;
+    for (int64_t root = 0; root < Nv; ++root) {
+      if (label[(size_t)root] >= 0) continue;
+      int64_t head = next;
+      label[(size_t)root] = (int32_t)next;
+      site_of[(size_t)next++] = (int32_t)root;
+      while (head < next) {
+        const int32_t v = site_of[(size_t)head++];
+        for (int k = 0; k < z; ++k) {
+          const int32_t w = g->adj[(size_t)v * z + k];
+          if (label[(size_t)w] < 0) {
+            label[(size_t)w] = (int32_t)next;
+            site_of[(size_t)next++] = w;
+          }
+        }
+      }
+    }
+    // class-sorted edge records (u, v, e, 0) in device numbering, canonical edge id e;
+    // inside a class ordered by the smaller endpoint (any order gives the same result)
+    const int64_t E = (int64_t)g->eu.size();
+    std::vector<int> &cs = p->class_start;
+    cs.assign((size_t)g->C + 1, 0);
+    for (int64_t q = 0; q < E; ++q) cs[(size_t)g->ecls[q] + 1]++;
+    for (int c = 0; c < g->C; ++c) cs[(size_t)c + 1] += cs[(size_t)c];
+    std::vector<int> fill(cs.begin(), cs.end() - 1);
+    std::vector<int4> &rec = p->rec;
+    rec.resize((size_t)E);
+    for (int64_t q = 0; q < E; ++q)
+      rec[(size_t)fill[(size_t)g->ecls[q]]++] =
+          make_int4(label[(size_t)g->eu[q]], label[(size_t)g->ev[q]], (int)q, 0);
+    for (int c = 0; c < g->C; ++c)
+      std::sort(rec.begin() + cs[(size_t)c], rec.begin() + cs[(size_t)c + 1],
+                [](const int4 &x, const int4 &y) {
+                  const int kx = std::min(x.x, x.y), ky = std::min(y.x, y.y);
+                  return kx != ky ? kx < ky : x.z < y.z;
+                });
+    // Neighbour lists of every record, slot-major: slot q < z-1 is the q-th neighbour of u
+    // other than v, slot z-1+q the q-th neighbour of v other than u (device numbering).
+    const int K = z - 1;
+    std::vector<int32_t> &nbr = p->nbr;
+    nbr.resize((size_t)2 * K * (size_t)E);
+    for (int64_t k = 0; k < E; ++k) {
+      const int32_t ends[2] = {rec[(size_t)k].x, rec[(size_t)k].y};
+      for (int side = 0; side < 2; ++side) {
+        const int32_t a_end = site_of[(size_t)ends[side]], b_end = site_of[(size_t)ends[1 - side]];
+        int q = 0;
+        for (int j = 0; j < z; ++j) {
+          const int32_t w = g->adj[(size_t)a_end * z + j];
+          if (w == b_end) continue;
+          nbr[(size_t)(side * K + q++) * (size_t)E + (size_t)k] = label[(size_t)w];
+        }
+      }
+    }
+    g->plan = std::move(p);
+  } catch (const std::bad_alloc &) {
+    return nullptr;
+  }
+  return g->plan;
+}
+
 int check_sim(const ka_sim *s)
 {
   if (!s) return fail(KA_EINVAL, "sim is NULL");
@@ -775,72 +853,31 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
     s->geom.N = (int)g->N;
     lattice_class_tables(g->d, s->lcls);
   } else {
-    // Device numbering of the vertices: breadth-first order, so the neighbours of vertices
-    // with nearby numbers have nearby numbers and gathers share cache lines.
-    const int64_t Nv = g->N;
-    const int z = g->z;
-    s->label.assign((size_t)Nv, -1);
-    std::vector<int32_t> site_of((size_t)Nv);
-    int64_t next = 0;
-    for (int64_t root = 0; root < Nv; ++root) {
-      if (s->label[(size_t)root] >= 0) continue;
-      int64_t head = next;
-      s->label[(size_t)root] = (int32_t)next;
-      site_of[(size_t)next++] = (int32_t)root;
-      while (head < next) {
-        const int32_t v = site_of[(size_t)head++];
-        for (int k = 0; k < z; ++k) {
-          const int32_t w = g->adj[(size_t)v * z + k];
-          if (s->label[(size_t)w] < 0) {
-            s->label[(size_t)w] = (int32_t)next;
-            site_of[(size_t)next++] = w;
-          }
-        }
-      }
+    const std::shared_ptr<const GraphPlan> plan = graph_plan(g);
+    if (!plan) {
+      free_device(s);
+      if (s->own_stream) (void)hipStreamDestroy(s->stream);
+      delete s;
+      return fail(KA_ENOMEM, "host allocation failed for the graph schedule");
     }
-    // class-sorted edge records (u, v, e, 0) in device numbering, canonical edge id e;
-    // inside a class ordered by the smaller endpoint (any order gives the same result)
-    const int64_t E = (int64_t)g->eu.size();
-    s->class_start.assign((size_t)g->C + 1, 0);
-    for (int64_t q = 0; q < E; ++q) s->class_start[(size_t)g->ecls[q] + 1]++;
-    for (int c = 0; c < g->C; ++c) s->class_start[(size_t)c + 1] += s->class_start[(size_t)c];
-    std::vector<int> fill(s->class_start.begin(), s->class_start.end() - 1);
-    std::vector<int4> rec((size_t)E);
-    for (int64_t q = 0; q < E; ++q)
-      rec[(size_t)fill[(size_t)g->ecls[q]]++] =
-          make_int4(s->label[(size_t)g->eu[q]], s->label[(size_t)g->ev[q]], (int)q, 0);
-    for (int c = 0; c < g->C; ++c)
-      std::sort(rec.begin() + s->class_start[(size_t)c], rec.begin() + s->class_start[(size_t)c + 1],
-                [](const int4 &x, const int4 &y) {
-                  const int kx = std::min(x.x, x.y), ky = std::min(y.x, y.y);
-                  return kx != ky ? kx < ky : x.z < y.z;
-                });
-    // Neighbour lists of every record, slot-major: slot q < z-1 is the q-th neighbour of u
-    // other than v, slot z-1+q the q-th neighbour of v other than u (device numbering).
-    const int K = z - 1;
-    std::vector<int32_t> nbr((size_t)2 * K * (size_t)E);
-    for (int64_t k = 0; k < E; ++k) {
-      const int32_t ends[2] = {rec[(size_t)k].x, rec[(size_t)k].y};
-      for (int side = 0; side < 2; ++side) {
-        const int32_t a_end = site_of[(size_t)ends[side]], b_end = site_of[(size_t)ends[1 - side]];
-        int q = 0;
-        for (int j = 0; j < z; ++j) {
-          const int32_t w = g->adj[(size_t)a_end * z + j];
-          if (w == b_end) continue;
-          nbr[(size_t)(side * K + q++) * (size_t)E + (size_t)k] = s->label[(size_t)w];
-        }
-      }
-    }
-    s->edges_total = (size_t)E;
+    // The sim keeps the plan alive, so the copies below may run after the graph is freed.
+    s->plan = plan;
+    const std::vector<int32_t> &site_of = plan->site_of;
+    const std::vector<int4> &rec = plan->rec;
+    const std::vector<int32_t> &nbr = plan->nbr;
+    const std::vector<int> &cs = plan->class_start;
+    s->edges_total = rec.size();
     e = dalloc(&s->nbr, nbr.size() * 4);
-    if (e == hipSuccess) e = hipMemcpy(s->nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&s->site_of, site_of.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = hipMemcpy(s->site_of, site_of.data(), site_of.size() * sizeof(int32_t), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = dalloc(&s->edges, rec.size() * sizeof(int4));
-    if (e == hipSuccess) e = dalloc(&s->class_start_d, s->class_start.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMemcpy(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = dalloc(&s->class_start_d, cs.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMemcpyAsync(s->nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
-      e = hipMemcpy(s->class_start_d, s->class_start.data(), s->class_start.size() * sizeof(int), hipMemcpyHostToDevice);
+      e = hipMemcpyAsync(s->site_of, site_of.data(), site_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(s->class_start_d, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) {
       free_device(s);
       if (s->own_stream) (void)hipStreamDestroy(s->stream);
@@ -1076,7 +1113,7 @@ extern "C" int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, i
     e = hipMemcpy(buf.data(), srcs[k], words * 8, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "ka_get_state copy");
     for (int64_t i = 0; i < s->N; ++i) {
-      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->label[(size_t)i];
+      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->plan->label[(size_t)i];
       for (int p = 0; p < s->planes; ++p)
         for (int w = 0; w < s->wpt; ++w)
           outs[k][(size_t)(p * s->wpt + w) * s->N + i] = buf[((size_t)p * s->N + el) * s->wpt + w];
@@ -1102,7 +1139,7 @@ extern "C" int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, co
   if (e != hipSuccess) return hip_fail(e, "ka_set_state");
   for (int k = 0; k < 3; ++k) {
     for (int64_t i = 0; i < s->N; ++i) {
-      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->label[(size_t)i];
+      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->plan->label[(size_t)i];
       for (int p = 0; p < s->planes; ++p)
         for (int w = 0; w < s->wpt; ++w)
           buf[((size_t)p * s->N + el) * s->wpt + w] = ins[k][(size_t)(p * s->wpt + w) * s->N + i];

@@ -4,11 +4,23 @@
 
 #include <stdint.h>
 
+#include <memory>
+#include <mutex>
 #include <utility>
 #include <vector>
 
 #include "ka.h"
 #include "ka_internal.h"
+
+// Device schedule of a general graph, in device numbering: built once per graph on its first
+// ka_init and copied to the device by every ka_init on that graph.
+struct GraphPlan {
+  std::vector<int32_t> label;     // device index of canonical vertex i
+  std::vector<int32_t> site_of;   // canonical vertex of device index
+  std::vector<int> class_start;   // [C+1]
+  std::vector<int4> rec;          // class-sorted (u, v, e, 0)
+  std::vector<int32_t> nbr;       // [2(z-1)][E] neighbour lists of rec
+};
 
 struct ka_graph {
   int lattice = 0;  // 1: hypercubic lattice (d, L); 0: general z-regular graph
@@ -18,6 +30,8 @@ struct ka_graph {
   int C = 0;
   std::vector<int32_t> adj;            // [N][z]
   std::vector<int32_t> eu, ev, ecls;   // canonical edges
+  mutable std::mutex plan_mu;
+  mutable std::shared_ptr<const GraphPlan> plan;   // general graphs, once built
 };
 
 struct ka_sim {
@@ -27,8 +41,7 @@ struct ka_sim {
   int64_t N = 0;
   ka::LatticeGeom geom{};
   ka::LatticeClasses lcls{};
-  std::vector<int> class_start;   // general graphs: [C+1]
-  std::vector<int32_t> label;     // general graphs: device index of canonical vertex i
+  std::shared_ptr<const GraphPlan> plan;   // general graphs: schedule (label, class_start, ...)
   // parameters
   int m = 0;
   int64_t K = 0;

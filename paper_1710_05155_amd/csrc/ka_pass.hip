@@ -10,6 +10,11 @@ using namespace dev;
 
 constexpr int kPassBlock = 256;
 constexpr int kObsBlock = 256;
+// Graph classes are uneven (greedy colouring): a class with fewer edges than this (over all
+// planes) runs in 64-thread workgroups, which spread it over more CUs; larger ones in
+// kPassBlock-thread workgroups.
+constexpr int kGraphSmallBlock = 64;
+constexpr long long kGraphSmallEdges = 65536;
 
 // ------------------------------------------------------------------------------------
 // Global-memory class pass kernels: one launch per (class, sweep), all planes at once.
@@ -36,13 +41,13 @@ __global__ __launch_bounds__(kPassBlock) void k_pass_lattice(PassLattice a, int 
                            a.key0, a.key1);
 }
 
-template <int Z, int WPT>
-__global__ __launch_bounds__(kPassBlock) void k_pass_graph(PassGraph a, int m)
+template <int Z, int WPT, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void k_pass_graph(PassGraph a, int m)
 {
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
   const int plane = lin / a.blocks_per_plane;
   const int blk = lin - plane * a.blocks_per_plane;
-  const int k = blk * kPassBlock + (int)threadIdx.x;
+  const int k = blk * BLOCK + (int)threadIdx.x;
   if (k >= a.count) return;
   const size_t off = (size_t)plane * (size_t)a.N * WPT;
   graph_edge<Z, WPT>(a.n + off, a.f + off, a.edges, a.nbr, a.stride, a.first + k, plane, m, a.t,
@@ -286,11 +291,21 @@ hipError_t launch_pass_lattice(const PassLattice &a, int m, int wpt, hipStream_t
   return hipGetLastError();
 }
 
-hipError_t launch_pass_graph(const PassGraph &a, int z, int m, int wpt, hipStream_t s)
+hipError_t launch_pass_graph(const PassGraph &args, int z, int m, int wpt, hipStream_t s)
 {
+  PassGraph a = args;
+  const bool small = (long long)a.count * a.planes < kGraphSmallEdges;
+  const int bs = small ? kGraphSmallBlock : kPassBlock;
+  a.blocks_per_plane = (a.count + bs - 1) / bs;
   const dim3 grid((unsigned)(a.blocks_per_plane * a.planes));
-  const dim3 block(kPassBlock);
-#define KA_GR(Z, W) hipLaunchKernelGGL((k_pass_graph<Z, W>), grid, block, 0, s, a, m)
+  const dim3 block((unsigned)bs);
+#define KA_GR(Z, W)                                                                        \
+  do {                                                                                     \
+    if (small)                                                                             \
+      hipLaunchKernelGGL((k_pass_graph<Z, W, kGraphSmallBlock>), grid, block, 0, s, a, m); \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_pass_graph<Z, W, kPassBlock>), grid, block, 0, s, a, m);       \
+  } while (0)
   switch (z * 4 + wpt) {
     case 3 * 4 + 1: KA_GR(3, 1); break;
     case 3 * 4 + 2: KA_GR(3, 2); break;

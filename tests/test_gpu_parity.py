@@ -261,3 +261,28 @@ def test_pair_sums_full_workload_properties():
     _, dens, ov, pers = ka.ka_observe(sim)
     assert S2[0] == int(ov.sum())
     assert (S2 >= 0).all() and (S11 >= 0).all()
+
+
+def test_graph_schedule_reused_and_outlives_graph(oracle):
+    """The device schedule of a general graph is built on the first ka_init and reused by
+    later ones; a sim keeps working after its graph is freed.  Two sims of one graph (the
+    second built from the cached schedule, the graph then freed under both) equal the
+    oracle bit for bit."""
+    N, z, m, R, seed = 3000, 4, 2, 128, 9
+    g = ka.ka_graph_rrg(N, z, seed)
+    adj, _, _, _ = ka.ka_graph_export(g)
+    og = oracle.graph_from_adjacency(adj)
+    K = ka.k_from_rho(N, 0.6)
+    _say(f"schedule reuse: RRG N={N} z={z} K={K} R={R}")
+    sims = [ka.ka_init_k(g, m, K, s, R) for s in (3, 4)]
+    ka.load().ka_graph_free(g.handle)
+    g._h = None
+    for s in sims:
+        s.graph = None
+    orcs = [oracle.Sim(og, m, K, s, range(R)) for s in (3, 4)]
+    for sim, orc in zip(sims, orcs):
+        ka.ka_sweep(sim, 7)
+        orc.sweep(7)
+        _state_equal(sim, orc)
+        _observe_equal(sim, orc)
+        sim.free()
