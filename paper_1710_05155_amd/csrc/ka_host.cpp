@@ -207,34 +207,42 @@ extern "C" int ka_graph_lattice(int d, int L, ka_graph **out)
   g->N = N;
   g->z = 2 * d;
   g->C = 4 * d;
-  try {
-    g->adj.resize((size_t)N * g->z);
-    g->eu.resize((size_t)N * d);
-    g->ev.resize((size_t)N * d);
-    g->ecls.resize((size_t)N * d);
-  } catch (...) {
-    delete g;
-    return fail(KA_ENOMEM, "host allocation failed");
-  }
-  int64_t stride[3] = {1, L, (int64_t)L * L};
-  for (int64_t i = 0; i < N; ++i) {
-    int x[3] = {0, 0, 0};
-    for (int k = 0; k < d; ++k) x[k] = (int)((i / stride[k]) % L);
-    int others_all = x[0] + x[1] + x[2];
-    for (int mu = 0; mu < d; ++mu) {
-      const int64_t up = i + (x[mu] + 1 < L ? stride[mu] : -(int64_t)(L - 1) * stride[mu]);
-      const int64_t dn = i + (x[mu] > 0 ? -stride[mu] : (int64_t)(L - 1) * stride[mu]);
-      g->adj[(size_t)i * g->z + 2 * mu] = (int32_t)up;
-      g->adj[(size_t)i * g->z + 2 * mu + 1] = (int32_t)dn;
-      const int64_t e = i * d + mu;
-      g->eu[e] = (int32_t)i;
-      g->ev[e] = (int32_t)up;
-      g->ecls[e] = 4 * mu + ((x[mu] + 2 * (others_all - x[mu])) & 3);
-    }
-  }
+  // The explicit adjacency and edge lists of a lattice are written on export only: the
+  // kernels compute neighbours and classes from coordinates.
   *out = g;
   return KA_OK;
 }
+
+namespace {
+
+// Adjacency [N][2d] (x+e_mu, x-e_mu per direction), canonical edges e = i*d + mu of
+// (x, x+e_mu) and their classes 4 mu + ((x_mu + 2 sum_{nu != mu} x_nu) mod 4); any output may
+// be NULL.
+void lattice_export(const ka_graph *g, int32_t *adj, int32_t *eu, int32_t *ev, int32_t *ecls)
+{
+  const int d = g->d, L = g->L, z = g->z;
+  const int64_t N = g->N;
+  const int64_t stride[3] = {1, L, (int64_t)L * L};
+  for (int64_t i = 0; i < N; ++i) {
+    int x[3] = {0, 0, 0};
+    for (int k = 0; k < d; ++k) x[k] = (int)((i / stride[k]) % L);
+    const int others_all = x[0] + x[1] + x[2];
+    for (int mu = 0; mu < d; ++mu) {
+      const int64_t up = i + (x[mu] + 1 < L ? stride[mu] : -(int64_t)(L - 1) * stride[mu]);
+      const int64_t dn = i + (x[mu] > 0 ? -stride[mu] : (int64_t)(L - 1) * stride[mu]);
+      if (adj) {
+        adj[(size_t)i * z + 2 * mu] = (int32_t)up;
+        adj[(size_t)i * z + 2 * mu + 1] = (int32_t)dn;
+      }
+      const int64_t e = i * d + mu;
+      if (eu) eu[e] = (int32_t)i;
+      if (ev) ev[e] = (int32_t)up;
+      if (ecls) ecls[e] = 4 * mu + ((x[mu] + 2 * (others_all - x[mu])) & 3);
+    }
+  }
+}
+
+}  // namespace
 
 extern "C" int ka_graph_rrg(int64_t N, int z, uint64_t graph_seed, ka_graph **out)
 {
@@ -424,7 +432,7 @@ extern "C" int ka_graph_info(const ka_graph *g, int64_t *N, int *z, int64_t *n_e
   if (!g) return fail(KA_EINVAL, "graph is NULL");
   if (N) *N = g->N;
   if (z) *z = g->z;
-  if (n_edges) *n_edges = (int64_t)g->eu.size();
+  if (n_edges) *n_edges = g->lattice ? g->N * g->d : (int64_t)g->eu.size();
   if (n_classes) *n_classes = g->C;
   return KA_OK;
 }
@@ -433,6 +441,10 @@ extern "C" int ka_graph_export(const ka_graph *g, int32_t *adj, int32_t *edge_u,
                                int32_t *edge_class)
 {
   if (!g) return fail(KA_EINVAL, "graph is NULL");
+  if (g->lattice) {
+    lattice_export(g, adj, edge_u, edge_v, edge_class);
+    return KA_OK;
+  }
   if (adj) std::memcpy(adj, g->adj.data(), g->adj.size() * sizeof(int32_t));
   if (edge_u) std::memcpy(edge_u, g->eu.data(), g->eu.size() * sizeof(int32_t));
   if (edge_v) std::memcpy(edge_v, g->ev.data(), g->ev.size() * sizeof(int32_t));

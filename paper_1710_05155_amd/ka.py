@@ -304,14 +304,14 @@ def ka_run(s: Sim, obs_times):
     return dens, ov, pers
 
 
-def ka_get_state(s: Sim):
+def ka_get_state(s: Sim, n: bool = True, n0: bool = True, f: bool = True):
+    """(n, n0, f, t) in the canonical [W][N] layout; an array not asked for comes back as None."""
     W = s.R // 64
-    n = np.empty((W, s.N), dtype=np.uint64)
-    n0 = np.empty((W, s.N), dtype=np.uint64)
-    f = np.empty((W, s.N), dtype=np.uint64)
+    arrs = [np.empty((W, s.N), dtype=np.uint64) if want else None for want in (n, n0, f)]
     t = ctypes.c_int64()
-    _check(load().ka_get_state(s.handle, _ptr(n), _ptr(n0), _ptr(f), ctypes.byref(t)))
-    return n, n0, f, t.value
+    ptrs = [_ptr(a) if a is not None else None for a in arrs]
+    _check(load().ka_get_state(s.handle, ptrs[0], ptrs[1], ptrs[2], ctypes.byref(t)))
+    return arrs[0], arrs[1], arrs[2], t.value
 
 
 def ka_set_state(s: Sim, n, n0, f, t: int) -> None:

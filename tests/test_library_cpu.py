@@ -99,3 +99,19 @@ def test_layered_graph_matches_oracle(oracle, d, L, M, seed):
     assert np.array_equal(adj, og.adj)
     assert np.array_equal(eu, og.eu) and np.array_equal(ev, og.ev) and np.array_equal(ec, og.ecls)
     assert g.C == og.C
+
+
+def test_size_limits():
+    """The largest lattices (N = 2^30) are accepted without building their edge lists on the
+    host; one step beyond is rejected, as are random regular graphs above 2^28 vertices."""
+    for d, L in [(3, 1024), (2, 32768)]:
+        g = ka.ka_graph_lattice(d, L)
+        assert g.N == 1 << 30 and g.E == d * (1 << 30) and g.C == 4 * d
+        assert ka.ka_footprint(g, 64) >= 3 * (1 << 30) * 8
+    for d, L in [(3, 1028), (2, 32772)]:
+        with pytest.raises(ka.KaError) as e:
+            ka.ka_graph_lattice(d, L)
+        assert e.value.code == ka.KA_EINVAL
+    with pytest.raises(ka.KaError) as e:
+        ka.ka_graph_rrg((1 << 28) + 2, 4, 1)
+    assert e.value.code == ka.KA_EINVAL
