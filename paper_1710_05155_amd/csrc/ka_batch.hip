@@ -18,23 +18,6 @@ namespace {
 
 using namespace dev;
 
-// Lower-endpoint sublattice number q of lattice class (mu, r): the residues of the other
-// directions are the base-4 digits of q, and a_mu = (r - 2 * their sum) mod 4.  Any
-// enumeration of the class's sublattices gives the same result (its edges commute).
-__device__ __forceinline__ int class_sublattice(int D, int mu, int r, int q)
-{
-  int a[3] = {0, 0, 0};
-  int rest = q, others = 0;
-  for (int nu = 0; nu < D; ++nu) {
-    if (nu == mu) continue;
-    a[nu] = rest & 3;
-    rest >>= 2;
-    others += a[nu];
-  }
-  a[mu] = (r - 2 * others) & 3;
-  return a[0] + 4 * a[1] + 16 * a[2];
-}
-
 template <int BLOCK, int WPT>
 __device__ __forceinline__ void run_lattice_tile(const BatchMember &mb, int local, int c, uint32_t t)
 {

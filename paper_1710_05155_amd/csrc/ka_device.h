@@ -70,12 +70,16 @@ struct Elem {
   u64 w[WPT];
 };
 
+// A word pair as one 16-byte vector, so that every load and store of an element is a single
+// 128-bit memory instruction.
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+
 template <int WPT>
 __device__ __forceinline__ Elem<WPT> ld(const u64 *base, int idx)
 {
   Elem<WPT> e;
   if constexpr (WPT == 2) {
-    const ulonglong2 v = reinterpret_cast<const ulonglong2 *>(base)[idx];
+    const u64x2 v = reinterpret_cast<const u64x2 *>(base)[idx];
     e.w[0] = v.x;
     e.w[1] = v.y;
   } else {
@@ -88,10 +92,10 @@ template <int WPT>
 __device__ __forceinline__ void st(u64 *base, int idx, const Elem<WPT> &e)
 {
   if constexpr (WPT == 2) {
-    ulonglong2 v;
+    u64x2 v;
     v.x = e.w[0];
     v.y = e.w[1];
-    reinterpret_cast<ulonglong2 *>(base)[idx] = v;
+    reinterpret_cast<u64x2 *>(base)[idx] = v;
   } else {
     base[idx] = e.w[0];
   }
@@ -221,6 +225,24 @@ struct Site {
   int idx;   // element index sub*P + pos
 };
 
+// Lower-endpoint sublattice number q of lattice class (mu, r): the residues of the other
+// directions are the base-4 digits of q (in increasing direction), and
+// a_mu = (r - 2 * their sum) mod 4.  A class owns 4^(D-1) such sublattices; any enumeration
+// of them gives the same result, since the class's edges commute.
+__device__ __forceinline__ int class_sublattice(int D, int mu, int r, int q)
+{
+  int a[3] = {0, 0, 0};
+  int rest = q, others = 0;
+  for (int nu = 0; nu < D; ++nu) {
+    if (nu == mu) continue;
+    a[nu] = rest & 3;
+    rest >>= 2;
+    others += a[nu];
+  }
+  a[mu] = (r - 2 * others) & 3;
+  return a[0] + 4 * a[1] + 16 * a[2];
+}
+
 __device__ __forceinline__ Site decode(const LatticeGeom &g, int D, int sub, int pos)
 {
   Site s;
@@ -309,14 +331,14 @@ __device__ __forceinline__ void lattice_stencil(const LatticeGeom &g, const Site
   }
 }
 
-// One lattice edge on the plane at base (global memory or LDS); shared by both paths.
+// One lattice edge (si, si + e_MU) on the plane at base (global memory or LDS), with si
+// already decoded; shared by all paths.
 template <int D, int MU, int WPT>
-__device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom &g, int sub,
-                                             int pos, int plane, int m, uint32_t t, uint32_t c,
-                                             uint32_t k0, uint32_t k1)
+__device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeGeom &g,
+                                                const Site &si, int plane, int m, uint32_t t,
+                                                uint32_t c, uint32_t k0, uint32_t k1)
 {
   constexpr int K = 2 * D - 1;
-  const Site si = decode(g, D, sub, pos);
   const Site sj = move_up(g, si, MU);
   int ii[K], jj[K];
   lattice_stencil<D, MU>(g, si, sj, ii, jj);
@@ -354,6 +376,15 @@ __device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom
     if (new_i) st<WPT>(fb, si.idx, fi);
     if (new_j) st<WPT>(fb, sj.idx, fj);
   }
+}
+
+// The same edge given by its sublattice and position.
+template <int D, int MU, int WPT>
+__device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom &g, int sub,
+                                             int pos, int plane, int m, uint32_t t, uint32_t c,
+                                             uint32_t k0, uint32_t k1)
+{
+  lattice_edge_at<D, MU, WPT>(nb, fb, g, decode(g, D, sub, pos), plane, m, t, c, k0, k1);
 }
 
 // One general-graph edge: entry k of the class-sorted edge list, record (u, v, e, 0) and

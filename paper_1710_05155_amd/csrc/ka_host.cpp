@@ -493,23 +493,6 @@ hipError_t dalloc(T **p, size_t bytes)
   return hipMalloc(reinterpret_cast<void **>(p), bytes ? bytes : 16);
 }
 
-// Lower-endpoint sublattices of lattice class c = 4*mu + r: residue vectors a with
-// (a_mu + 2 * sum_{nu != mu} a_nu) mod 4 == r, in increasing sub code.
-void lattice_class_tables(int d, ka::LatticeClasses &t)
-{
-  t.nsub = d == 2 ? 4 : 16;
-  const int nsubs = d == 2 ? 16 : 64;
-  for (int c = 0; c < 4 * d; ++c) {
-    const int mu = c >> 2, r = c & 3;
-    int k = 0;
-    for (int sub = 0; sub < nsubs; ++sub) {
-      const int a[3] = {sub & 3, (sub >> 2) & 3, (sub >> 4) & 3};
-      const int others = a[0] + a[1] + a[2] - a[mu];
-      if (((a[mu] + 2 * others) & 3) == r) t.sub[c][k++] = sub;
-    }
-  }
-}
-
 // Element index of canonical site i in the lattice device layout.
 inline int64_t lattice_element(const ka::LatticeGeom &g, int64_t i)
 {
@@ -590,10 +573,9 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t)
     a.f = s->f;
     a.g = s->geom;
     a.mu = c >> 2;
-    a.nsub = s->lcls.nsub;
-    for (int q = 0; q < a.nsub; ++q) a.sub[q] = s->lcls.sub[c][q];
     a.planes = s->planes;
-    const int per_plane = a.nsub * 64 * ((s->geom.P + 63) / 64);  // whole 64-position chunks
+    const int nsub = s->geom.d == 2 ? 4 : 16;   // lower-endpoint sublattices per class
+    const int per_plane = nsub * 64 * ((s->geom.P + 63) / 64);  // whole 64-position chunks
     a.blocks_per_plane = (per_plane + 255) / 256;
     a.t = t;
     a.c = (uint32_t)c;
@@ -658,7 +640,6 @@ hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
   a.f = s->f;
   a.n0 = s->n0;
   a.g = s->geom;
-  a.cls = s->lcls;
   a.edges = s->edges;
   a.nbr = s->nbr;
   a.stride = s->edges_total;
@@ -863,7 +844,6 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
     s->geom.Q = g->L / 4;
     s->geom.P = g->d == 2 ? s->geom.Q * s->geom.Q : s->geom.Q * s->geom.Q * s->geom.Q;
     s->geom.N = (int)g->N;
-    lattice_class_tables(g->d, s->lcls);
   } else {
     const std::shared_ptr<const GraphPlan> plan = graph_plan(g);
     if (!plan) {

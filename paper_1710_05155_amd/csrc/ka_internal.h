@@ -28,19 +28,11 @@ struct LatticeGeom {
   int N;        // L^d
 };
 
-// Lower-endpoint sublattices of each class (4^(d-1) of them, increasing sub code).
-struct LatticeClasses {
-  int nsub;               // 4^(d-1)
-  int sub[12][16];        // [class][k]
-};
-
 struct PassLattice {
   u64 *n;
   u64 *f;
   LatticeGeom g;
   int mu;
-  int nsub;
-  int sub[16];
   int planes;
   int blocks_per_plane;
   uint32_t t, c, key0, key1;
@@ -67,7 +59,6 @@ struct SweepLds {
   const u64 *n0;
   // lattice
   LatticeGeom g;
-  LatticeClasses cls;
   // graph
   const int4 *edges;         // all edges sorted by class
   const int32_t *nbr;        // [2(z-1)][E]

@@ -9,6 +9,9 @@ namespace {
 using namespace dev;
 
 constexpr int kLdsBlock = 1024;
+// Edges per thread and class on a lattice in LDS: a plane that fits (N * wpt <= 9984 words
+// per array) has at most 2496 edges per class.
+constexpr int kLdsSlots = 3;
 
 template <int WPT>
 __device__ void lds_observe(const SweepLds &a, const u64 *sn, const u64 *sf, int plane,
@@ -99,21 +102,40 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int
   lds_load<WPT>(a, sn, sf, plane);
   int qo = 0;
   lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)a.t0, cnt);
-  const int per_class = a.cls.nsub * a.g.P;
+  constexpr int nsub = D == 2 ? 4 : 16;   // lower-endpoint sublattices per class
+  const int per_class = nsub * a.g.P;
+  // This thread's edges are the same in every class: slot j is edge k = tid + j * blockDim of
+  // the class, the q-th lower-endpoint sublattice at position pos.  The divisions and the
+  // block coordinates of pos are done once, here; per class only the residues change.
+  const int tid = (int)threadIdx.x;
+  int slot_q[kLdsSlots];
+  Site slot_site[kLdsSlots];
+#pragma unroll
+  for (int j = 0; j < kLdsSlots; ++j) {
+    const int k = tid + j * kLdsBlock;
+    const int q = k / a.g.P;
+    slot_q[j] = q;
+    slot_site[j] = decode(a.g, D, 0, k - q * a.g.P);   // idx = pos, residues 0
+  }
   for (int s = 0; s < a.n_sweeps; ++s) {
     const uint32_t t = a.t0 + (uint32_t)s;
     for (int c = 0; c < a.C; ++c) {
       const int mu = c >> 2;
-      for (int k = (int)threadIdx.x; k < per_class; k += (int)blockDim.x) {
-        const int q = k / a.g.P;
-        const int pos = k - q * a.g.P;
-        const int sub = a.cls.sub[c][q];
+#pragma unroll
+      for (int j = 0; j < kLdsSlots; ++j) {
+        if (tid + j * kLdsBlock >= per_class) break;
+        const int sub = class_sublattice(D, mu, c & 3, slot_q[j]);
+        Site si = slot_site[j];
+        si.a[0] = sub & 3;
+        si.a[1] = (sub >> 2) & 3;
+        si.a[2] = (sub >> 4) & 3;
+        si.idx += sub * a.g.P;
         if (mu == 0)
-          lattice_edge<D, 0, WPT>(sn, sf, a.g, sub, pos, plane, m, t, (uint32_t)c, a.key0, a.key1);
+          lattice_edge_at<D, 0, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1);
         else if (mu == 1)
-          lattice_edge<D, 1, WPT>(sn, sf, a.g, sub, pos, plane, m, t, (uint32_t)c, a.key0, a.key1);
+          lattice_edge_at<D, 1, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1);
         else if constexpr (D == 3)
-          lattice_edge<D, 2, WPT>(sn, sf, a.g, sub, pos, plane, m, t, (uint32_t)c, a.key0, a.key1);
+          lattice_edge_at<D, 2, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1);
       }
       __syncthreads();
     }
@@ -185,6 +207,7 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
     if (e == hipSuccess)                                                          \
       hipLaunchKernelGGL((k_sweep_lds_graph<Z, W>), grid, block, lds_bytes, s, a, m); \
   } while (0)
+  if (lattice && (a.g.d == 2 ? 4 : 16) * a.g.P > kLdsSlots * kLdsBlock) return hipErrorInvalidValue;
   if (lattice) {
     if (a.g.d == 2) {
       if (wpt == 2) KA_LDS_L(2, 2); else KA_LDS_L(2, 1);

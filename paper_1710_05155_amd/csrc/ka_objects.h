@@ -40,7 +40,6 @@ struct ka_sim {
   int z = 0, C = 0;
   int64_t N = 0;
   ka::LatticeGeom geom{};
-  ka::LatticeClasses lcls{};
   std::shared_ptr<const GraphPlan> plan;   // general graphs: schedule (label, class_start, ...)
   // parameters
   int m = 0;

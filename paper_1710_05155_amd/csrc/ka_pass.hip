@@ -30,14 +30,18 @@ __global__ __launch_bounds__(kPassBlock) void k_pass_lattice(PassLattice a, int 
   const int plane = lin / a.blocks_per_plane;
   const int blk = lin - plane * a.blocks_per_plane;
   const int gid = blk * kPassBlock + (int)threadIdx.x;
-  const int span = a.nsub * 64;            // threads per 64-position chunk
+  constexpr int nsub = D == 2 ? 4 : 16;   // lower-endpoint sublattices per class
+  const int span = nsub * 64;              // threads per 64-position chunk
   const int chunk = gid / span;
   const int rem = gid - chunk * span;
-  const int q = rem >> 6;
+  // Waves are 64-thread aligned and span is a multiple of 64, so q is the same on every lane
+  // of the wave: take it (and the sublattice) in scalar registers.
+  const int q = __builtin_amdgcn_readfirstlane(rem >> 6);
   const int pos = chunk * 64 + (rem & 63);
   if (pos >= a.g.P) return;
+  const int sub = class_sublattice(D, MU, (int)(a.c & 3u), q);
   const size_t off = (size_t)plane * (size_t)a.g.N * WPT;
-  lattice_edge<D, MU, WPT>(a.n + off, a.f + off, a.g, a.sub[q], pos, plane, m, a.t, a.c,
+  lattice_edge<D, MU, WPT>(a.n + off, a.f + off, a.g, sub, pos, plane, m, a.t, a.c,
                            a.key0, a.key1);
 }
 
