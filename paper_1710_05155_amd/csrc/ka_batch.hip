@@ -40,6 +40,7 @@ __device__ __forceinline__ void run_lattice_tile(const BatchMember &mb, int loca
   g.Q = mb.Q;
   g.P = mb.P;
   g.N = mb.N;
+  g.qinv = mb.qinv;
   const size_t off = (size_t)plane * (size_t)mb.N * WPT;
   u64 *n = mb.n + off, *f = mb.f + off;
   if (mb.d == 2) {

@@ -409,6 +409,7 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
   m.L = s->geom.L;
   m.Q = s->geom.Q;
   m.P = s->geom.P;
+  m.qinv = s->geom.qinv;
   m.N = (int)s->N;
   m.z = s->z;
   m.m = s->m;

@@ -243,17 +243,23 @@ __device__ __forceinline__ int class_sublattice(int D, int mu, int r, int q)
   return a[0] + 4 * a[1] + 16 * a[2];
 }
 
+// n / Q for 0 <= n < 2^31, by the multiply in lattice_qinv.
+__device__ __forceinline__ int div_q(const LatticeGeom &g, int n)
+{
+  return (int)__umul64hi((u64)(unsigned)n << 1, g.qinv);
+}
+
 __device__ __forceinline__ Site decode(const LatticeGeom &g, int D, int sub, int pos)
 {
   Site s;
   s.a[0] = sub & 3;
   s.a[1] = (sub >> 2) & 3;
   s.a[2] = (sub >> 4) & 3;
-  s.p[0] = pos % g.Q;
-  const int rest = pos / g.Q;
+  const int rest = div_q(g, pos);
+  s.p[0] = pos - rest * g.Q;
   if (D == 3) {
-    s.p[1] = rest % g.Q;
-    s.p[2] = rest / g.Q;
+    s.p[2] = div_q(g, rest);
+    s.p[1] = rest - s.p[2] * g.Q;
   } else {
     s.p[1] = rest;
     s.p[2] = 0;

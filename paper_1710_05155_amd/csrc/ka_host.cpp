@@ -844,6 +844,7 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
     s->geom.Q = g->L / 4;
     s->geom.P = g->d == 2 ? s->geom.Q * s->geom.Q : s->geom.Q * s->geom.Q * s->geom.Q;
     s->geom.N = (int)g->N;
+    s->geom.qinv = ka::lattice_qinv(s->geom.Q);
   } else {
     const std::shared_ptr<const GraphPlan> plan = graph_plan(g);
     if (!plan) {

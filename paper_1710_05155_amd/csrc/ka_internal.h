@@ -26,7 +26,16 @@ struct LatticeGeom {
   int Q;        // L / 4
   int P;        // Q^d, elements per sublattice
   int N;        // L^d
+  unsigned long long qinv;   // lattice_qinv(Q): division by Q as a multiply
 };
+
+// ceil(2^63 / Q).  For 0 <= n < 2^31 and 1 <= Q < 2^31, n / Q = high 64 bits of
+// (2n) * qinv: with qinv = 2^63/Q + e, 0 <= e < 1, the product over 2^64 is n/Q + n e / 2^63
+// and n e / 2^63 < 1/Q, which is below the distance from n/Q up to the next integer.
+inline unsigned long long lattice_qinv(int Q)
+{
+  return ((1ull << 63) + (unsigned long long)Q - 1ull) / (unsigned long long)Q;
+}
 
 struct PassLattice {
   u64 *n;
@@ -148,6 +157,7 @@ struct BatchMember {
   const int *class_start;      // graphs: [C+1]
   int kind;                    // 0 lattice, 1 graph
   int d, L, Q, P, N;           // lattice geometry (N for both)
+  unsigned long long qinv;     // lattice: lattice_qinv(Q)
   int z, m, C, planes, wpt;
   uint32_t key0, key1;
   uint32_t t0;

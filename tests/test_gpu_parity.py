@@ -70,6 +70,10 @@ LATTICE_CASES = [
     (3, 8, 5, 0.5, 64),
     (3, 12, 2, 0.6, 192),
     (3, 16, 3, 0.85, 256),
+    # classes of more than 1024 edges: 2 or 3 edges per thread in the LDS path
+    (2, 96, 2, 0.7, 64),
+    (2, 68, 1, 0.6, 128),
+    (3, 20, 3, 0.85, 64),
 ]
 
 

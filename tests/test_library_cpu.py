@@ -115,3 +115,18 @@ def test_size_limits():
     with pytest.raises(ka.KaError) as e:
         ka.ka_graph_rrg((1 << 28) + 2, 4, 1)
     assert e.value.code == ka.KA_EINVAL
+
+
+def test_division_by_multiply_is_exact():
+    """The lattice kernels divide site positions by Q = L/4 as a multiply: n / Q is the high
+    64 bits of (2n) * ceil(2^63 / Q).  Exact for 0 <= n < 2^31 and every Q a lattice can have
+    (1..8192); checked at the multiples of Q and their neighbours, where rounding would fail."""
+    rng = np.random.default_rng(0)
+    for Q in list(range(1, 300)) + [int(q) for q in rng.integers(300, 8193, 200)] + [8191, 8192]:
+        M = ((1 << 63) + Q - 1) // Q
+        ks = np.unique(np.concatenate([np.arange(0, 64), rng.integers(0, (2**31 - 1) // Q, 64),
+                                       [(2**31 - 1) // Q]]))
+        for k in ks.tolist():
+            for n in (k * Q - 1, k * Q, k * Q + 1, k * Q + Q - 1):
+                if 0 <= n < 2**31:
+                    assert (2 * n * M) >> 64 == n // Q, (Q, n)
