@@ -245,7 +245,7 @@ typedef struct {
   int64_t n_sweeps;          /* total sweeps                                            */
   const int64_t *obs_times;  /* sweep indices in [0, n_sweeps], non-decreasing; copied;  */
   int n_obs;                 /* NULL/0: one observation at n_sweeps                     */
-  int keep_sim;              /* 1: keep the final sim for ka_server_take_sim            */
+  int keep_sim;              /* 1: keep the final sim for ka_server_take_sim             */
 } ka_job_desc;
 
 /* Server with a device-memory budget (bytes) and at most max_active concurrent jobs
@@ -263,8 +263,16 @@ int ka_server_poll(ka_server *sv, int64_t *job_ids, int max_ids, int *n);
 int ka_server_result(ka_server *sv, int64_t job_id, int64_t *density, int64_t *overlap,
                      int64_t *persistence, double *wait_s, double *latency_s);
 
-/* Hand over the final sim of a completed job submitted with keep_sim (caller frees it). */
+/* Hand over the final sim of a completed job submitted with keep_sim; the caller frees it
+ * with ka_free.  A kept sim belongs to the caller once its job completes and no longer counts
+ * against the budget.  If the server created its own stream, the sim moves to a stream of its
+ * own, so it may outlive the server. */
 int ka_server_take_sim(ka_server *sv, int64_t job_id, ka_sim **out);
+
+/* Forget a completed job: drop its results and free its kept sim if it was not taken.
+ * Completed jobs' results are otherwise kept until ka_server_free.  KA_ESTATE if the job is
+ * not complete (or already released). */
+int ka_server_release(ka_server *sv, int64_t job_id);
 
 /* Block until every submitted job has completed. */
 int ka_server_wait_idle(ka_server *sv);

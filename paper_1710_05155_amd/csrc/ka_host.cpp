@@ -1029,6 +1029,21 @@ int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out)
   return KA_OK;
 }
 
+// Bind the sim to a new stream that it owns (after waiting for its old one if asked to).
+int ka_sim_take_own_stream(ka_sim *s, bool wait)
+{
+  if (!s) return fail(KA_EINVAL, "sim is NULL");
+  DeviceGuard dg(s->device);
+  hipError_t e = wait ? hipStreamSynchronize(s->stream) : hipSuccess;
+  hipStream_t fresh = nullptr;
+  if (e == hipSuccess) e = hipStreamCreate(&fresh);
+  if (e != hipSuccess) return hip_fail(e, "stream");
+  if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  s->stream = fresh;
+  s->own_stream = true;
+  return KA_OK;
+}
+
 extern "C" int ka_observe_pairs(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *count)
 {
   int rc = check_sim(s);

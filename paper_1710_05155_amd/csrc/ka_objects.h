@@ -85,4 +85,7 @@ void ka_set_error(const char *msg);
 int ka_batch_release_member(ka_batch *b, ka_sim *s);
 // Counts of ka_observe enqueued on the sim's stream into pinned host memory (3 * R values).
 int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out);
+// Move a sim onto a new stream that it owns (its old stream may then be destroyed).  With
+// wait = false the caller guarantees that no work of the sim is pending on the old stream.
+int ka_sim_take_own_stream(ka_sim *s, bool wait);
 

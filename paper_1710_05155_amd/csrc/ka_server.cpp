@@ -10,10 +10,13 @@
 //   4. detaches members whose segment completed, enqueues their observation (counts copied
 //      into pinned host memory) and either re-adds them for the next segment or marks them
 //      finishing;
-//   5. retires finishing jobs whose last copy has landed (event), frees their device memory
-//      and publishes them to ka_server_poll.
-// All HIP calls happen on the worker thread; the API functions only touch queues under a
-// mutex.
+//   5. retires finishing jobs whose last copy has landed (event): moves their counts out of
+//      pinned memory, frees their device memory (a kept sim stays; it belongs to the caller
+//      from then on and no longer counts against the budget, so that waiting for all jobs
+//      before taking their sims cannot block admission) and publishes them to
+//      ka_server_poll.
+// HIP calls happen on the worker thread, except in ka_server_take_sim / ka_server_release,
+// which touch only a completed job's own sim; the API functions share state under a mutex.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -60,7 +63,8 @@ struct Job {
   size_t footprint = 0;
   double attempts = 0;               // N * R * sweeps
   ka_sim *sim = nullptr;
-  unsigned long long *pinned = nullptr;  // [n_obs][3][R]
+  unsigned long long *pinned = nullptr;  // [n_obs][3][R] while the job runs
+  std::vector<int64_t> counts;           // [n_obs][3][R] once it is complete
   hipEvent_t done_ev = nullptr;
   int rc = KA_OK;
   Clock::time_point t_submit, t_admit, t_done;
@@ -92,7 +96,7 @@ struct ka_server {
   std::map<int, std::unique_ptr<Job>> active;  // by batch slot
   std::vector<std::unique_ptr<Job>> finishing;
   std::deque<hipEvent_t> inflight;
-  size_t used = 0;
+  size_t used = 0;                   // device bytes of admitted, unfinished jobs
   // statistics (guarded by mu)
   double attempts_done = 0;
   int peak_active = 0;
@@ -102,9 +106,15 @@ struct ka_server {
 
 namespace {
 
+// A completed job: counts out of pinned memory, device memory freed unless the sim is kept.
 void release_job_memory(Job *j)
 {
-  if (j->sim && !j->keep) {
+  if (j->pinned) {
+    if (j->rc == KA_OK) j->counts.assign(j->pinned, j->pinned + j->obs.size() * 3u * (size_t)j->R);
+    (void)hipHostFree(j->pinned);
+    j->pinned = nullptr;
+  }
+  if (j->sim && (!j->keep || j->rc != KA_OK)) {
     ka_free(j->sim);
     j->sim = nullptr;
   }
@@ -390,13 +400,15 @@ extern "C" int ka_server_result(ka_server *sv, int64_t job_id, int64_t *density,
   if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
   Job *j = it->second.get();
   if (j->rc != KA_OK) return sfail(j->rc, "job %lld failed", (long long)job_id);
+  if (j->counts.size() != j->obs.size() * 3u * (size_t)j->R)
+    return sfail(KA_ESTATE, "job %lld has no counts", (long long)job_id);
   const size_t R = (size_t)j->R;
   for (size_t q = 0; q < j->obs.size(); ++q)
     for (size_t b = 0; b < R; ++b) {
-      const unsigned long long *row = j->pinned + q * 3u * R;
-      if (density) density[q * R + b] = (int64_t)row[b];
-      if (overlap) overlap[q * R + b] = (int64_t)row[R + b];
-      if (persistence) persistence[q * R + b] = (int64_t)row[2 * R + b];
+      const int64_t *row = j->counts.data() + q * 3u * R;
+      if (density) density[q * R + b] = row[b];
+      if (overlap) overlap[q * R + b] = row[R + b];
+      if (persistence) persistence[q * R + b] = row[2 * R + b];
     }
   if (wait_s) *wait_s = std::chrono::duration<double>(j->t_admit - j->t_submit).count();
   if (latency_s) *latency_s = std::chrono::duration<double>(j->t_done - j->t_submit).count();
@@ -406,13 +418,42 @@ extern "C" int ka_server_result(ka_server *sv, int64_t job_id, int64_t *density,
 extern "C" int ka_server_take_sim(ka_server *sv, int64_t job_id, ka_sim **out)
 {
   if (!sv || !out) return sfail(KA_EINVAL, "NULL argument");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  auto it = sv->finished.find(job_id);
-  if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
-  Job *j = it->second.get();
-  if (!j->keep || !j->sim) return sfail(KA_ESTATE, "job %lld kept no sim", (long long)job_id);
-  *out = j->sim;
-  j->sim = nullptr;
+  ka_sim *sim = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->finished.find(job_id);
+    if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
+    Job *j = it->second.get();
+    if (!j->keep || !j->sim) return sfail(KA_ESTATE, "job %lld kept no sim", (long long)job_id);
+    sim = j->sim;
+    j->sim = nullptr;
+  }
+  // The server's own stream ends with the server, so the sim gets a stream of its own.  The
+  // job is complete (its last copy has landed), so nothing of the sim is pending.
+  if (sv->own_stream) {
+    const int rc = ka_sim_take_own_stream(sim, false);
+    if (rc != KA_OK) {
+      ka_free(sim);
+      return rc;
+    }
+  }
+  *out = sim;
+  return KA_OK;
+}
+
+extern "C" int ka_server_release(ka_server *sv, int64_t job_id)
+{
+  if (!sv) return sfail(KA_EINVAL, "server is NULL");
+  std::unique_ptr<Job> jp;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto it = sv->finished.find(job_id);
+    if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
+    jp = std::move(it->second);
+    sv->finished.erase(it);
+    sv->done_ids.erase(std::remove(sv->done_ids.begin(), sv->done_ids.end(), job_id), sv->done_ids.end());
+  }
+  if (jp->sim) ka_free(jp->sim);   // the job is complete: nothing of it runs on the device
   return KA_OK;
 }
 

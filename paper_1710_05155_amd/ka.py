@@ -29,7 +29,7 @@ SYMBOLS = (
     "ka_timing", "ka_sim_path", "ka_free", "ka_last_error",
     "ka_batch_create", "ka_batch_add", "ka_batch_run", "ka_batch_steps_left", "ka_batch_poll",
     "ka_batch_wait_all", "ka_batch_set_option", "ka_batch_info", "ka_batch_free",
-    "ka_server_create", "ka_server_submit", "ka_server_poll", "ka_server_result", "ka_server_take_sim",
+    "ka_server_create", "ka_server_submit", "ka_server_poll", "ka_server_result", "ka_server_take_sim", "ka_server_release",
     "ka_server_wait_idle", "ka_server_stats", "ka_server_free",
 )
 
@@ -112,6 +112,7 @@ def load():
         "ka_server_poll": ([P, P, I, P], I),
         "ka_server_result": ([P, I64, P, P, P, P, P], I),
         "ka_server_take_sim": ([P, I64, PP], I),
+        "ka_server_release": ([P, I64], I),
         "ka_server_wait_idle": ([P], I),
         "ka_server_stats": ([P, P, P, P, P], I),
         "ka_server_free": ([P], None),
@@ -476,7 +477,11 @@ def ka_server_poll(sv: Server, max_ids: int = 4096) -> list:
 
 
 def ka_server_result(sv: Server, job_id: int):
-    _, n_obs, R = sv.jobs[job_id]
+    info = sv.jobs.get(int(job_id))
+    if info is None:   # not submitted here, or released: the library reports the error
+        _check(load().ka_server_result(sv.handle, int(job_id), None, None, None, None, None))
+        raise KaError(KA_ESTATE, f"job {job_id} is unknown")
+    _, n_obs, R = info
     dens = np.empty((n_obs, R), dtype=np.int64)
     ov = np.empty((n_obs, R), dtype=np.int64)
     pers = np.empty((n_obs, R), dtype=np.int64)
@@ -491,6 +496,12 @@ def ka_server_take_sim(sv: Server, job_id: int) -> Sim:
     h = ctypes.c_void_p()
     _check(load().ka_server_take_sim(sv.handle, int(job_id), ctypes.byref(h)))
     return Sim(h, sv.jobs[job_id][0], sv.stream)
+
+
+def ka_server_release(sv: Server, job_id: int) -> None:
+    """Forget a completed job (its results and, if not taken, its kept sim)."""
+    _check(load().ka_server_release(sv.handle, int(job_id)))
+    sv.jobs.pop(int(job_id), None)
 
 
 def ka_server_wait_idle(sv: Server) -> None:

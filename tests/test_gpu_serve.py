@@ -111,3 +111,39 @@ def test_server_rejects_oversized_job(graphs):
         ka.ka_server_submit(sv, graphs[("lat", 2, 64)], 2, 0.7, 1, 64, 10)
     assert e.value.code == ka.KA_EINVAL
     sv.free()
+
+
+def test_release_and_taken_sim_outlives_server(graphs):
+    """ka_server_release forgets a completed job (results and untaken kept sim); a taken
+    sim moves off the server's own stream, so it keeps running after the server is freed and
+    still equals the solo run."""
+    g = graphs[("lat", 2, 16)]
+    m, rho, R, sweeps = 1, 0.5, 128, 10
+    _say("serve: release and a taken sim after ka_server_free")
+    sv = ka.ka_server_create(1 << 34, 8)
+    a = ka.ka_server_submit(sv, g, m, rho, 21, R, sweeps, obs_times=[0, sweeps], keep_sim=True)
+    b = ka.ka_server_submit(sv, g, m, rho, 22, R, sweeps, keep_sim=True)
+    c = ka.ka_server_submit(sv, g, m, rho, 23, R, sweeps)
+    ka.ka_server_wait_idle(sv)
+    res_a = ka.ka_server_result(sv, a)
+    sim_a = ka.ka_server_take_sim(sv, a)
+    ka.ka_server_release(sv, b)            # kept sim never taken: freed here
+    ka.ka_server_release(sv, c)
+    for jid in (b, c):
+        with pytest.raises(ka.KaError) as e:
+            ka.ka_server_result(sv, jid)
+        assert e.value.code == ka.KA_ESTATE
+    with pytest.raises(ka.KaError):
+        ka.ka_server_release(sv, c)
+    assert set(ka.ka_server_poll(sv)) == {a}
+    sv.free()
+    ka.ka_sweep(sim_a, 5)
+    _, dens, ov, pers = ka.ka_observe(sim_a)
+    state = ka.ka_get_state(sim_a)
+    sim_a.free()
+    (d0, o0, p0), _ = _solo(g, m, rho, R, 21, sweeps, [0, sweeps])
+    assert np.array_equal(res_a["overlap"], o0) and np.array_equal(res_a["persistence"], p0)
+    (d1, o1, p1), solo_state = _solo(g, m, rho, R, 21, sweeps + 5, [sweeps + 5])
+    assert np.array_equal(ov, o1[0]) and np.array_equal(pers, p1[0]) and np.array_equal(dens, d1[0])
+    for x, y in zip(state, solo_state):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
