@@ -60,9 +60,10 @@ def class_pass_bytes(w, N, W):
     return None
 
 
-def measured_traffic(kernel_sources, counters_file):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, or None when the
-    kernel sources no longer hash to the ones the counters were taken with."""
+def measured_traffic(kernel_sources, counters_file, key="traffic_bytes_per_launch"):
+    """A figure from a committed rocprofv3 counter summary (by default the HBM bytes per
+    launch), or None when the kernel sources no longer hash to the ones the counters were
+    taken with."""
     import hashlib
     try:
         kv = {}
@@ -77,7 +78,7 @@ def measured_traffic(kernel_sources, counters_file):
                 h.update(fh.read())
         if h.hexdigest() != kv.get("source_sha256"):
             return None
-        return float(kv["traffic_bytes_per_launch"])
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
 
@@ -406,12 +407,28 @@ def main():
         w = dict(w, R=args.replicas, desc=w["desc"] + f" [replicas overridden: {args.replicas}]")
     N, R, sweeps = g.N, w["R"], w["sweeps"]
     if args.calibrate_copy_mib > 0:
+        # A plain device-to-device copy (rocclr copyBuffer) and fill of known size: the scale
+        # for hardware byte counters, and the box's practical streaming rates.
         nbytes = args.calibrate_copy_mib << 20
         src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read + {nbytes} bytes written")
+        best = {"copy": float("inf"), "fill": float("inf")}
+        for _ in range(3):
+            for kind in ("copy", "fill"):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                if kind == "copy":
+                    dst.copy_(src)
+                else:
+                    dst.fill_(7)
+                b.record()
+                torch.cuda.synchronize()
+                best[kind] = min(best[kind], a.elapsed_time(b) / 1000.0)
+        log(f"calibration rates: copy {2 * nbytes / best['copy'] / 1e12:.2f} TB/s (read + write), "
+            f"fill {nbytes / best['fill'] / 1e12:.2f} TB/s")
         del src, dst
     W = R // 64
     grid = obs_grid(w)
@@ -512,12 +529,15 @@ def main():
         achieved = B / avg_s / 1e9
         csrc = os.path.join(ROOT, "paper_1710_05155_amd", "csrc")
         traffic = None
+        valu = None
         if args.workload == "cubic128" and R == 256:
-            traffic = measured_traffic([os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")],
-                                       os.path.join(ROOT, "profiles", "k_pass_lattice_cubic128.counters.txt"))
+            srcs = [os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")]
+            cfile = os.path.join(ROOT, "profiles", "k_pass_lattice_cubic128.counters.txt")
+            traffic = measured_traffic(srcs, cfile)
+            valu = measured_traffic(srcs, cfile, key="valu_busy_pct")
         result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                               "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                              "kernel": kernel, "avg_launch_us": avg_s * 1e6,
+                              "valu_busy_pct": valu, "kernel": kernel, "avg_launch_us": avg_s * 1e6,
                               "bytes_per_launch": B, "launches": pass_launches,
                               "sampled_launch_us": pass_ms_total / pass_timed * 1000.0 if pass_timed else None}
     if not args.no_cpu_baseline:
