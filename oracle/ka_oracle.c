@@ -382,13 +382,24 @@ int ko_accept_bit(uint64_t seed, int64_t t, int c, int64_t e, int64_t b)
     return (int)((half >> (b & 63)) & 1);
 }
 
+/* Shared-noise variant (the paper's multispin step applies one random choice to every
+ * replica of a word, Sec. 3.2): one acceptance bit per (sweep t, class c, edge e) common to
+ * all replicas, bit 0 of output word 0 of Philox(t, c, e, 0xFFFFFFFF). */
+int ko_accept_bit_shared(uint64_t seed, int64_t t, int c, int64_t e)
+{
+    uint64_t half = ko_philox_half((uint32_t)t, (uint32_t)c, (uint32_t)e, 0xFFFFFFFFu, seed, 0);
+    return (int)(half & 1);
+}
+
 /* n_sweeps sweeps (t = t0 .. t0+n_sweeps-1) of the replicas listed in reps[0..nrep-1];
  * occ and moved are nrep*N, row q belonging to replica reps[q].  Classes are visited in
- * increasing c, edges of a class in increasing canonical id.  Replicas are independent
- * chains, so they are distributed over threads. */
+ * increasing c, edges of a class in increasing canonical id.  shared selects the
+ * shared-noise acceptance bits.  Each replica's run reads only its own row and the
+ * (deterministic) bits, so replicas are distributed over threads. */
 void ko_run(int64_t N, int z, const int32_t *adj, int64_t E, const int32_t *eu,
             const int32_t *ev, const int32_t *ecls, int C, int m, uint64_t seed, int64_t nrep,
-            const int64_t *reps, int64_t t0, int64_t n_sweeps, uint8_t *occ, uint8_t *moved)
+            const int64_t *reps, int64_t t0, int64_t n_sweeps, uint8_t *occ, uint8_t *moved,
+            int shared)
 {
     /* edges bucketed by class, each bucket in increasing e */
     int64_t *start = (int64_t *)calloc((size_t)C + 1, sizeof(int64_t));
@@ -408,7 +419,8 @@ void ko_run(int64_t N, int z, const int32_t *adj, int64_t E, const int32_t *eu,
             for (int c = 0; c < C; ++c)
                 for (int64_t k = start[c]; k < start[c + 1]; ++k) {
                     int64_t e = order[k];
-                    int r = ko_accept_bit(seed, t, c, e, b);
+                    int r = shared ? ko_accept_bit_shared(seed, t, c, e)
+                                   : ko_accept_bit(seed, t, c, e, b);
                     if (r) ko_edge(z, m, adj, eu[e], ev[e], r, o, mv);
                 }
     }

@@ -48,7 +48,9 @@ def load():
         _lib.ko_pass.argtypes = [I64, I32, P, I64, P, P, P, I32, I32, I64, P, P, P]
         _lib.ko_accept_bit.argtypes = [U64, I64, I32, I64, I64]
         _lib.ko_accept_bit.restype = I32
-        _lib.ko_run.argtypes = [I64, I32, P, I64, P, P, P, I32, I32, U64, I64, P, I64, I64, P, P]
+        _lib.ko_accept_bit_shared.argtypes = [U64, I64, I32, I64]
+        _lib.ko_accept_bit_shared.restype = I32
+        _lib.ko_run.argtypes = [I64, I32, P, I64, P, P, P, I32, I32, U64, I64, P, I64, I64, P, P, I32]
         _lib.ko_threads.restype = I32
         _lib.ko_layered.argtypes = [I32, I32, I32, U64, P]
         _lib.ko_layered.restype = I32
@@ -207,15 +209,22 @@ def accept_bit(seed: int, t: int, c: int, e: int, b: int) -> int:
     return int(load().ko_accept_bit(seed, t, c, e, b))
 
 
+def accept_bit_shared(seed: int, t: int, c: int, e: int) -> int:
+    """Shared-noise variant: the one acceptance bit of edge e, class c, sweep t for every
+    replica."""
+    return int(load().ko_accept_bit_shared(seed, t, c, e))
+
+
 def run(g: Graph, m: int, seed: int, replicas, occ: np.ndarray, moved: np.ndarray,
-        t0: int, n_sweeps: int) -> None:
-    """Sweeps t0 .. t0+n_sweeps-1 in place on occ/moved (rows = listed replicas)."""
+        t0: int, n_sweeps: int, shared: bool = False) -> None:
+    """Sweeps t0 .. t0+n_sweeps-1 in place on occ/moved (rows = listed replicas); shared
+    selects the shared-noise acceptance bits (one per edge for all replicas)."""
     lib = load()
     reps = np.ascontiguousarray(np.asarray(list(replicas), dtype=np.int64))
     assert occ.shape == (reps.shape[0], g.N) and moved.shape == occ.shape
     assert occ.flags["C_CONTIGUOUS"] and moved.flags["C_CONTIGUOUS"]
     lib.ko_run(g.N, g.z, _p(g.adj), g.E, _p(g.eu), _p(g.ev), _p(g.ecls), g.C, m, seed,
-               reps.shape[0], _p(reps), t0, n_sweeps, _p(occ), _p(moved))
+               reps.shape[0], _p(reps), t0, n_sweeps, _p(occ), _p(moved), 1 if shared else 0)
 
 
 def threads() -> int:
@@ -274,8 +283,9 @@ def unpack(words: np.ndarray) -> np.ndarray:
 class Sim:
     """Convenience: a set of replicas of one (graph, m, K, seed) run by the oracle."""
 
-    def __init__(self, g: Graph, m: int, K: int, seed: int, replicas):
+    def __init__(self, g: Graph, m: int, K: int, seed: int, replicas, shared: bool = False):
         self.g, self.m, self.K, self.seed = g, m, int(K), seed
+        self.shared = bool(shared)
         self.replicas = [int(b) for b in replicas]
         self.occ = init(g, K, seed, self.replicas)
         self.occ0 = self.occ.copy()
@@ -284,7 +294,8 @@ class Sim:
 
     def sweep(self, n: int) -> None:
         if n > 0:
-            run(self.g, self.m, self.seed, self.replicas, self.occ, self.moved, self.t, n)
+            run(self.g, self.m, self.seed, self.replicas, self.occ, self.moved, self.t, n,
+                self.shared)
             self.t += n
 
     def observe(self):

@@ -13,7 +13,11 @@ mathematics fix (no implementation exists to compare against):
   product of one-walker class matrices; m = z-1 (no constraint): the exclusion process is
   a stirring process, so E[overlap] = sum_ij n0_i P_t(i,j) n0_j (self-duality);
 - schedule bookkeeping: split invariance and replica independence;
-- observables at t = 0: overlap = persistence = density = K, C(0) = 1.
+- observables at t = 0: overlap = persistence = density = K, C(0) = 1;
+- shared-noise variant (one acceptance bit per edge for all replicas, as the paper's
+  multispin step applies one random choice to all replicas of a word): replicas started
+  equal stay equal, and at m = z-1 every replica is moved by one and the same permutation of
+  the sites, found by following single particles.
 """
 import itertools
 import math
@@ -308,6 +312,50 @@ def test_every_replica_has_its_own_noise(oracle):
     assert len({row.tobytes() for row in occ}) == 256
     occ0 = oracle.init(g, 20, 42, range(256))
     assert len({row.tobytes() for row in occ0}) == 256
+
+
+@pytest.mark.parametrize("kind", ["lattice", "rrg"])
+def test_shared_noise_couples_equal_replicas(oracle, kind):
+    """With shared noise, replicas started from the same state stay identical for ever,
+    while with independent noise they separate; replicas started apart stay conserved."""
+    g = oracle.lattice(2, 8) if kind == "lattice" else oracle.rrg(60, 4, 3)
+    rng = np.random.default_rng(5)
+    start = (rng.random(g.N) < 0.55).astype(np.uint8)
+    other = (rng.random(g.N) < 0.55).astype(np.uint8)
+    for shared in (True, False):
+        occ = np.stack([start, start, other, start]).astype(np.uint8)
+        moved = np.zeros_like(occ)
+        oracle.run(g, 2, 17, [0, 1, 2, 63], occ, moved, 0, 25, shared=shared)
+        same = [np.array_equal(occ[0], occ[k]) and np.array_equal(moved[0], moved[k]) for k in (1, 3)]
+        assert all(same) if shared else not any(same)
+        assert int(occ[2].sum()) == int(other.sum()) and int(occ[0].sum()) == int(start.sum())
+        assert not np.array_equal(occ[0], start)
+
+
+@pytest.mark.parametrize("kind", ["lattice", "rrg"])
+def test_shared_noise_stirring_is_one_permutation(oracle, kind):
+    """At m = z-1 an accepted edge always swaps its two sites' contents (equal contents make
+    the swap a no-op), so with shared noise every replica is moved by one permutation pi of
+    the sites.  pi is found by following a single particle from each site (K = 1 replicas);
+    then a many-particle replica must end as its start moved by pi, and its moved-ever mask
+    must cover every site whose final content differs from its start."""
+    g = oracle.lattice(2, 8) if kind == "lattice" else oracle.rrg(48, 3, 9)
+    N = g.N
+    rng = np.random.default_rng(11)
+    many = (rng.random(N) < 0.5).astype(np.uint8)
+    occ = np.zeros((N + 1, N), dtype=np.uint8)
+    occ[np.arange(N), np.arange(N)] = 1
+    occ[N] = many
+    moved = np.zeros_like(occ)
+    oracle.run(g, g.z - 1, 23, range(N + 1), occ, moved, 0, 7, shared=True)
+    pi = occ[:N].argmax(axis=1)
+    assert (occ[:N].sum(axis=1) == 1).all()
+    assert sorted(pi.tolist()) == list(range(N)), "not a permutation"
+    expect = np.zeros(N, dtype=np.uint8)
+    expect[pi] = many
+    assert np.array_equal(occ[N], expect)
+    assert (moved[N][occ[N] != many] == 1).all()
+    assert (pi != np.arange(N)).any()
 
 
 # ------------------------------------------------------------------------ four-point sums
