@@ -160,9 +160,16 @@ int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t *K, int *m
  *                  2 = whole sweep loop inside one workgroup per word plane with the plane in
  *                      LDS (only if it fits; KA_EINVAL otherwise).  Results are identical.
  *   KA_OPT_TIMING: k > 0 brackets every k-th class-pass launch with HIP events on the sim's
- *                  stream (for per-kernel durations, read with ka_timing); 0 = off. */
+ *                  stream (for per-kernel durations, read with ka_timing); 0 = off.
+ *   KA_OPT_NOISE:  0 (default) = an independent acceptance bit per replica, edge and sweep;
+ *                  1 = shared noise: one bit per (sweep t, class c, edge e) for every replica,
+ *                      bit 0 of output word 0 of Philox(t, c, e, 0xFFFFFFFF).  This is the
+ *                      paper's multispin step (Sec. 3.2), which applies one random choice to
+ *                      all replicas of a word.  Replicas are then coupled: replicas started
+ *                      equal stay equal.  Applies to the sweeps that follow. */
 #define KA_OPT_PATH 1
 #define KA_OPT_TIMING 2
+#define KA_OPT_NOISE 3
 int ka_set_option(ka_sim *s, int option, int64_t value);
 
 /* Class-pass launches so far, and among them the number bracketed by events and their

@@ -44,12 +44,12 @@ __device__ __forceinline__ void run_lattice_tile(const BatchMember &mb, int loca
   const size_t off = (size_t)plane * (size_t)mb.N * WPT;
   u64 *n = mb.n + off, *f = mb.f + off;
   if (mb.d == 2) {
-    if (mu == 0) lattice_edge<2, 0, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-    else lattice_edge<2, 1, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
+    if (mu == 0) lattice_edge<2, 0, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise);
+    else lattice_edge<2, 1, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise);
   } else {
-    if (mu == 0) lattice_edge<3, 0, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-    else if (mu == 1) lattice_edge<3, 1, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
-    else lattice_edge<3, 2, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1);
+    if (mu == 0) lattice_edge<3, 0, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise);
+    else if (mu == 1) lattice_edge<3, 1, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise);
+    else lattice_edge<3, 2, WPT>(n, f, g, sub, pos, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise);
   }
 }
 
@@ -67,10 +67,10 @@ __device__ __forceinline__ void run_graph_tile(const BatchMember &mb, int local,
   u64 *n = mb.n + off, *f = mb.f + off;
   const size_t st = (size_t)mb.stride;
   switch (mb.z) {
-    case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 5: graph_edge<5, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
-    case 6: graph_edge<6, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1); break;
+    case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
+    case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
+    case 5: graph_edge<5, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
+    case 6: graph_edge<6, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
     default: break;
   }
 }

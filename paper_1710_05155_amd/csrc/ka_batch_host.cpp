@@ -418,6 +418,7 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
   m.wpt = s->wpt;
   m.key0 = (uint32_t)s->seed;
   m.key1 = (uint32_t)(s->seed >> 32);
+  m.noise = s->noise;
   m.t0 = (uint32_t)s->t;
   m.s_begin = b->step;
   m.s_end = b->step + (int64_t)s->C * n_sweeps;

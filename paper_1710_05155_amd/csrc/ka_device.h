@@ -47,18 +47,21 @@ __device__ __forceinline__ u64 lo_half(uint4 o) { return (u64)o.x | ((u64)o.y <<
 __device__ __forceinline__ u64 hi_half(uint4 o) { return (u64)o.z | ((u64)o.w << 32); }
 
 // Acceptance words of the WPT words of plane `plane` for edge e of class c in sweep t:
-// word w uses half (w & 1) of Philox(t, c, e, w >> 1).
+// word w uses half (w & 1) of Philox(t, c, e, w >> 1).  With shared noise (noise != 0) every
+// replica takes the same bit: bit 0 of output word 0 of Philox(t, c, e, 0xFFFFFFFF).  One
+// Philox call either way; only its counter and the final selection differ.
 template <int WPT>
 __device__ __forceinline__ void accept_words(uint32_t t, uint32_t c, uint32_t e, int plane,
-                                             uint32_t k0, uint32_t k1, u64 (&r)[WPT])
+                                             uint32_t k0, uint32_t k1, int noise, u64 (&r)[WPT])
 {
+  const uint32_t w3 = noise ? 0xFFFFFFFFu : (WPT == 2 ? (uint32_t)plane : (uint32_t)plane >> 1);
+  const uint4 o = philox10(make_uint4(t, c, e, w3), k0, k1);
+  const u64 all = (o.x & 1u) ? ~0ull : 0ull;
   if constexpr (WPT == 2) {
-    const uint4 o = philox10(make_uint4(t, c, e, (uint32_t)plane), k0, k1);
-    r[0] = lo_half(o);
-    r[1] = hi_half(o);
+    r[0] = noise ? all : lo_half(o);
+    r[1] = noise ? all : hi_half(o);
   } else {
-    const uint4 o = philox10(make_uint4(t, c, e, (uint32_t)plane >> 1), k0, k1);
-    r[0] = (plane & 1) ? hi_half(o) : lo_half(o);
+    r[0] = noise ? all : ((plane & 1) ? hi_half(o) : lo_half(o));
   }
 }
 
@@ -342,7 +345,7 @@ __device__ __forceinline__ void lattice_stencil(const LatticeGeom &g, const Site
 template <int D, int MU, int WPT>
 __device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeGeom &g,
                                                 const Site &si, int plane, int m, uint32_t t,
-                                                uint32_t c, uint32_t k0, uint32_t k1)
+                                                uint32_t c, uint32_t k0, uint32_t k1, int noise)
 {
   constexpr int K = 2 * D - 1;
   const Site sj = move_up(g, si, MU);
@@ -358,7 +361,7 @@ __device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeG
   }
   const uint32_t e = (uint32_t)canonical(g, D, si) * (uint32_t)D + (uint32_t)MU;
   u64 r[WPT];
-  accept_words<WPT>(t, c, e, plane, k0, k1, r);
+  accept_words<WPT>(t, c, e, plane, k0, k1, noise, r);
   u64 d[WPT];
   exchange<K, WPT>(ni, nj, xi, xj, r, m, d);
   u64 any = 0;
@@ -388,9 +391,9 @@ __device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeG
 template <int D, int MU, int WPT>
 __device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom &g, int sub,
                                              int pos, int plane, int m, uint32_t t, uint32_t c,
-                                             uint32_t k0, uint32_t k1)
+                                             uint32_t k0, uint32_t k1, int noise)
 {
-  lattice_edge_at<D, MU, WPT>(nb, fb, g, decode(g, D, sub, pos), plane, m, t, c, k0, k1);
+  lattice_edge_at<D, MU, WPT>(nb, fb, g, decode(g, D, sub, pos), plane, m, t, c, k0, k1, noise);
 }
 
 // One general-graph edge: entry k of the class-sorted edge list, record (u, v, e, 0) and
@@ -400,7 +403,7 @@ __device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom
 template <int Z, int WPT>
 __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int4 *edges, const int32_t *nbr,
                                            size_t stride, int k, int plane, int m, uint32_t t,
-                                           uint32_t c, uint32_t k0, uint32_t k1)
+                                           uint32_t c, uint32_t k0, uint32_t k1, int noise)
 {
   constexpr int K = Z - 1;
   const int4 E = edges[k];
@@ -420,7 +423,7 @@ __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int4 *edges, 
     xv[q] = ld<WPT>(nb, iv[q]);
   }
   u64 r[WPT];
-  accept_words<WPT>(t, c, (uint32_t)E.z, plane, k0, k1, r);
+  accept_words<WPT>(t, c, (uint32_t)E.z, plane, k0, k1, noise, r);
   u64 d[WPT];
   exchange<K, WPT>(ni, nj, xu, xv, r, m, d);
   u64 any = 0;

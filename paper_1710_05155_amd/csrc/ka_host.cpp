@@ -581,6 +581,7 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t)
     a.c = (uint32_t)c;
     a.key0 = k0;
     a.key1 = k1;
+    a.noise = s->noise;
     err = ka::launch_pass_lattice(a, s->m, s->wpt, s->stream);
   } else {
     ka::PassGraph a{};
@@ -597,6 +598,7 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t)
     a.c = (uint32_t)c;
     a.key0 = k0;
     a.key1 = k1;
+    a.noise = s->noise;
     err = a.count > 0 ? ka::launch_pass_graph(a, s->z, s->m, s->wpt, s->stream) : hipSuccess;
   }
   if (timed) {
@@ -654,6 +656,7 @@ hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
   a.R = s->R;
   a.key0 = (uint32_t)s->seed;
   a.key1 = (uint32_t)(s->seed >> 32);
+  a.noise = s->noise;
   return ka::launch_sweep_lds(a, s->lattice != 0, s->z, s->m, s->wpt, s->lds_bytes, s->stream);
 }
 
@@ -1185,6 +1188,11 @@ extern "C" int ka_set_option(ka_sim *s, int option, int64_t value)
   if (option == KA_OPT_TIMING) {
     if (value < 0) return fail(KA_EINVAL, "timing interval must be >= 0");
     s->timing_every = value;
+    return KA_OK;
+  }
+  if (option == KA_OPT_NOISE) {
+    if (value != 0 && value != 1) return fail(KA_EINVAL, "noise must be 0 or 1");
+    s->noise = (int)value;
     return KA_OK;
   }
   return fail(KA_EINVAL, "unknown option %d", option);

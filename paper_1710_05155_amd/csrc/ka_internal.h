@@ -42,6 +42,7 @@ struct PassLattice {
   u64 *f;
   LatticeGeom g;
   int mu;
+  int noise;                 // 0: acceptance bit per replica, 1: shared by all replicas
   int planes;
   int blocks_per_plane;
   uint32_t t, c, key0, key1;
@@ -55,6 +56,7 @@ struct PassGraph {
   size_t stride;             // E
   int first;                 // first edge of the class
   int count;                 // edges in the class
+  int noise;                 // 0: acceptance bit per replica, 1: shared by all replicas
   int N;
   int planes;
   int blocks_per_plane;
@@ -75,6 +77,7 @@ struct SweepLds {
   const int *class_start;    // [C+1]
   int N;
   int C;
+  int noise;                 // 0: acceptance bit per replica, 1: shared by all replicas
   uint32_t t0;
   int n_sweeps;
   // observations: absolute sweep indices (non-decreasing), rows of out [n_obs][3][R]
@@ -159,6 +162,7 @@ struct BatchMember {
   int d, L, Q, P, N;           // lattice geometry (N for both)
   unsigned long long qinv;     // lattice: lattice_qinv(Q)
   int z, m, C, planes, wpt;
+  int noise;                   // 0: acceptance bit per replica, 1: shared by all replicas
   uint32_t key0, key1;
   uint32_t t0;
   int tiles_per_plane;         // tiles of BLOCK threads per plane (graphs: largest class)

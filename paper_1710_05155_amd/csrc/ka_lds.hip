@@ -131,11 +131,14 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int
         si.a[2] = (sub >> 4) & 3;
         si.idx += sub * a.g.P;
         if (mu == 0)
-          lattice_edge_at<D, 0, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1);
+          lattice_edge_at<D, 0, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1,
+                                     a.noise);
         else if (mu == 1)
-          lattice_edge_at<D, 1, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1);
+          lattice_edge_at<D, 1, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1,
+                                     a.noise);
         else if constexpr (D == 3)
-          lattice_edge_at<D, 2, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1);
+          lattice_edge_at<D, 2, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1,
+                                     a.noise);
       }
       __syncthreads();
     }
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_graph(SweepLds a, int m
       const int b0 = a.class_start[c], b1 = a.class_start[c + 1];
       for (int k = b0 + (int)threadIdx.x; k < b1; k += (int)blockDim.x)
         graph_edge<Z, WPT>(sn, sf, a.edges, a.nbr, a.stride, k, plane, m, t, (uint32_t)c, a.key0,
-                           a.key1);
+                           a.key1, a.noise);
       __syncthreads();
     }
     lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)t + 1, cnt);

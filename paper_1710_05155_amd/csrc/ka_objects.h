@@ -69,6 +69,7 @@ struct ka_sim {
   // options and timing
   bool init_checked = false;
   int path_opt = 0;
+  int noise = 0;                  // KA_OPT_NOISE
   size_t lds_bytes = 0;
   bool lds_fits = false;
   int64_t timing_every = 0;

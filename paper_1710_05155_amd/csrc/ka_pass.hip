@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kPassBlock) void k_pass_lattice(PassLattice a, int 
   const int sub = class_sublattice(D, MU, (int)(a.c & 3u), q);
   const size_t off = (size_t)plane * (size_t)a.g.N * WPT;
   lattice_edge<D, MU, WPT>(a.n + off, a.f + off, a.g, sub, pos, plane, m, a.t, a.c,
-                           a.key0, a.key1);
+                           a.key0, a.key1, a.noise);
 }
 
 template <int Z, int WPT, int BLOCK>
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(BLOCK) void k_pass_graph(PassGraph a, int m)
   if (k >= a.count) return;
   const size_t off = (size_t)plane * (size_t)a.N * WPT;
   graph_edge<Z, WPT>(a.n + off, a.f + off, a.edges, a.nbr, a.stride, a.first + k, plane, m, a.t,
-                     a.c, a.key0, a.key1);
+                     a.c, a.key0, a.key1, a.noise);
 }
 
 template <int WPT>

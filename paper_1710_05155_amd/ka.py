@@ -20,6 +20,7 @@ KA_EDEVICE = -3
 KA_ESTATE = -4
 KA_OPT_PATH = 1
 KA_OPT_TIMING = 2
+KA_OPT_NOISE = 3
 
 # Every symbol include/ka.h declares.
 SYMBOLS = (

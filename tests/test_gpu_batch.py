@@ -180,3 +180,28 @@ def test_batch_errors(graphs):
     ka.ka_sweep(s, 1)                      # detached: usable again
     b.free()
     b2.free()
+
+
+def test_batch_shared_noise_members_equal_solo(graphs):
+    """Members with shared noise (KA_OPT_NOISE = 1) next to members with independent noise
+    end bit-identical to their solo runs with the same setting."""
+    _say("batch: mixed noise settings")
+    shared = [k % 2 == 0 for k in range(len(MEMBERS))]
+    ref = []
+    for spec, g, sh in zip(MEMBERS, graphs, shared):
+        s = _make(spec, g)
+        ka.ka_set_option(s, ka.KA_OPT_NOISE, int(sh))
+        ka.ka_sweep(s, spec[7])
+        ref.append(ka.ka_get_state(s))
+        s.free()
+    b = ka.ka_batch_create(64)
+    sims = []
+    for spec, g, sh in zip(MEMBERS, graphs, shared):
+        s = _make(spec, g)
+        ka.ka_set_option(s, ka.KA_OPT_NOISE, int(sh))
+        ka.ka_batch_add(b, s, spec[7])
+        sims.append(s)
+    ka.ka_batch_wait_all(b)
+    states = [ka.ka_get_state(s) for s in sims]
+    b.free()
+    _assert_same(states, ref)

@@ -290,3 +290,65 @@ def test_graph_schedule_reused_and_outlives_graph(oracle):
         _state_equal(sim, orc)
         _observe_equal(sim, orc)
         sim.free()
+
+
+SHARED_CASES = [
+    # kind, size, z-or-d, m, rho, R
+    ("lattice", 12, 2, 2, 0.6, 128),
+    ("lattice", 8, 3, 3, 0.8, 64),
+    ("lattice", 64, 2, 2, 0.7, 256),
+    ("rrg", 300, 4, 2, 0.6, 192),
+    ("rrg", 200, 6, 5, 0.5, 64),
+]
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("kind,size,zd,m,rho,R", SHARED_CASES)
+def test_shared_noise_parity(oracle, kind, size, zd, m, rho, R, path):
+    """KA_OPT_NOISE = 1 (one acceptance bit per edge for all replicas) equals the oracle's
+    shared-noise run bit for bit, on both kernel paths."""
+    if kind == "lattice":
+        g, og = ka.ka_graph_lattice(zd, size), oracle.lattice(zd, size)
+    else:
+        g = ka.ka_graph_rrg(size, zd, 5)
+        og = oracle.graph_from_adjacency(oracle.rrg_adjacency(size, zd, 5)[0])
+    K = oracle.k_from_rho(og.N, rho)
+    _say(f"shared noise: {kind} {size} m={m} R={R} path={path}")
+    sim = ka.ka_init_k(g, m, K, 77, R)
+    try:
+        ka.ka_set_option(sim, ka.KA_OPT_PATH, path)
+    except ka.KaError:
+        sim.free()
+        pytest.skip("this instance does not fit the LDS-resident path on this device")
+    ka.ka_set_option(sim, ka.KA_OPT_NOISE, 1)
+    orc = oracle.Sim(og, m, K, 77, range(R), shared=True)
+    for n in (1, 3, 5):
+        ka.ka_sweep(sim, n)
+        orc.sweep(n)
+        _state_equal(sim, orc)
+        _observe_equal(sim, orc)
+    sim.free()
+
+
+def test_shared_noise_couples_equal_replicas_on_gpu():
+    """With shared noise, replicas set to the same state stay equal (checked over all word
+    positions of a 3-word state), and switching back to independent noise separates them."""
+    g = ka.ka_graph_lattice(3, 12)
+    sim = ka.ka_init(g, 3, 0.8, 9, 192)
+    n, n0, f, _ = ka.ka_get_state(sim)
+    first = (n[0] & np.uint64(1)).astype(bool)
+    word = np.where(first, np.uint64(0xFFFFFFFFFFFFFFFF), np.uint64(0))
+    same = np.repeat(word[None, :], 3, axis=0)
+    ka.ka_set_state(sim, same, same, np.zeros_like(same), 0)
+    ka.ka_set_option(sim, ka.KA_OPT_NOISE, 1)
+    ka.ka_sweep(sim, 20)
+    n, _, f, _ = ka.ka_get_state(sim)
+    for arr in (n, f):
+        assert ((arr == np.uint64(0)) | (arr == np.uint64(0xFFFFFFFFFFFFFFFF))).all()
+        assert (arr == arr[0][None, :]).all()
+    assert not np.array_equal(n[0], word)
+    ka.ka_set_option(sim, ka.KA_OPT_NOISE, 0)
+    ka.ka_sweep(sim, 5)
+    n, _, _, _ = ka.ka_get_state(sim)
+    assert not ((n == np.uint64(0)) | (n == np.uint64(0xFFFFFFFFFFFFFFFF))).all()
+    sim.free()
