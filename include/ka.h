@@ -89,8 +89,9 @@ int ka_graph_from_adjacency(int64_t N, int z, const int32_t *adj, ka_graph **out
 /* Sizes: N sites, degree z, number of edges (N*z/2), number of edge classes C. */
 int ka_graph_info(const ka_graph *g, int64_t *N, int *z, int64_t *n_edges, int *n_classes);
 
-/* Copies (any may be NULL): adj [N][z], and per canonical edge e: its endpoints
- * edge_u[e] < ... (lattices: edge_u = x, edge_v = x + e_mu) and its class edge_class[e]. */
+/* Copies (any may be NULL): adj [N][z], and per canonical edge e its endpoints and its class
+ * edge_class[e].  General graphs: edge_u[e] < edge_v[e]; lattices: edge_u = x and
+ * edge_v = x + e_mu (the lattice lists are computed here, on the host, on each call). */
 int ka_graph_export(const ka_graph *g, int32_t *adj, int32_t *edge_u, int32_t *edge_v,
                     int32_t *edge_class);
 
