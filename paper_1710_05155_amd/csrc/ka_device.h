@@ -340,26 +340,23 @@ __device__ __forceinline__ void lattice_stencil(const LatticeGeom &g, const Site
   }
 }
 
-// One lattice edge (si, si + e_MU) on the plane at base (global memory or LDS), with si
-// already decoded; shared by all paths.
-template <int D, int MU, int WPT>
-__device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeGeom &g,
-                                                const Site &si, int plane, int m, uint32_t t,
-                                                uint32_t c, uint32_t k0, uint32_t k1, int noise)
+// The exchange across one edge (i, j) with canonical id e, class c, sweep t, on the plane at
+// base nb (moved-ever words at fb; global memory or LDS), given the element indices of i,
+// j and of their K neighbours other than the partner; shared by every path.
+template <int K, int WPT>
+__device__ __forceinline__ void edge_update(u64 *nb, u64 *fb, int i, int j, const int (&ii)[K],
+                                            const int (&jj)[K], uint32_t e, int plane, int m,
+                                            uint32_t t, uint32_t c, uint32_t k0, uint32_t k1,
+                                            int noise)
 {
-  constexpr int K = 2 * D - 1;
-  const Site sj = move_up(g, si, MU);
-  int ii[K], jj[K];
-  lattice_stencil<D, MU>(g, si, sj, ii, jj);
-  Elem<WPT> ni = ld<WPT>(nb, si.idx);
-  Elem<WPT> nj = ld<WPT>(nb, sj.idx);
+  Elem<WPT> ni = ld<WPT>(nb, i);
+  Elem<WPT> nj = ld<WPT>(nb, j);
   Elem<WPT> xi[K], xj[K];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     xi[k] = ld<WPT>(nb, ii[k]);
     xj[k] = ld<WPT>(nb, jj[k]);
   }
-  const uint32_t e = (uint32_t)canonical(g, D, si) * (uint32_t)D + (uint32_t)MU;
   u64 r[WPT];
   accept_words<WPT>(t, c, e, plane, k0, k1, noise, r);
   u64 d[WPT];
@@ -368,12 +365,12 @@ __device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeG
 #pragma unroll
   for (int w = 0; w < WPT; ++w) any |= d[w];
   if (any) {
-    st<WPT>(nb, si.idx, ni);
-    st<WPT>(nb, sj.idx, nj);
+    st<WPT>(nb, i, ni);
+    st<WPT>(nb, j, nj);
     // f only gains a bit the first time a site changes in a replica, so it is stored
     // only then: over a run a word is rewritten at most 64 times.
-    Elem<WPT> fi = ld<WPT>(fb, si.idx);
-    Elem<WPT> fj = ld<WPT>(fb, sj.idx);
+    Elem<WPT> fi = ld<WPT>(fb, i);
+    Elem<WPT> fj = ld<WPT>(fb, j);
     u64 new_i = 0, new_j = 0;
 #pragma unroll
     for (int w = 0; w < WPT; ++w) {
@@ -382,9 +379,36 @@ __device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeG
       fi.w[w] |= d[w];
       fj.w[w] |= d[w];
     }
-    if (new_i) st<WPT>(fb, si.idx, fi);
-    if (new_j) st<WPT>(fb, sj.idx, fj);
+    if (new_i) st<WPT>(fb, i, fi);
+    if (new_j) st<WPT>(fb, j, fj);
   }
+}
+
+// Element indices and canonical id of the lattice edge (si, si + e_MU): i, j, the 2D-1
+// other neighbours of each, and e = i_canonical * D + MU.
+template <int D, int MU>
+__device__ __forceinline__ void lattice_edge_indices(const LatticeGeom &g, const Site &si, int &i,
+                                                     int &j, int (&ii)[2 * D - 1],
+                                                     int (&jj)[2 * D - 1], uint32_t &e)
+{
+  const Site sj = move_up(g, si, MU);
+  lattice_stencil<D, MU>(g, si, sj, ii, jj);
+  i = si.idx;
+  j = sj.idx;
+  e = (uint32_t)canonical(g, D, si) * (uint32_t)D + (uint32_t)MU;
+}
+
+// One lattice edge (si, si + e_MU), with si already decoded.
+template <int D, int MU, int WPT>
+__device__ __forceinline__ void lattice_edge_at(u64 *nb, u64 *fb, const LatticeGeom &g,
+                                                const Site &si, int plane, int m, uint32_t t,
+                                                uint32_t c, uint32_t k0, uint32_t k1, int noise)
+{
+  constexpr int K = 2 * D - 1;
+  int i, j, ii[K], jj[K];
+  uint32_t e;
+  lattice_edge_indices<D, MU>(g, si, i, j, ii, jj, e);
+  edge_update<K, WPT>(nb, fb, i, j, ii, jj, e, plane, m, t, c, k0, k1, noise);
 }
 
 // The same edge given by its sublattice and position.
@@ -413,38 +437,7 @@ __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int4 *edges, 
     iu[q] = nbr[(size_t)q * stride + (size_t)k];
     iv[q] = nbr[(size_t)(K + q) * stride + (size_t)k];
   }
-  const int u = E.x, v = E.y;
-  Elem<WPT> ni = ld<WPT>(nb, u);
-  Elem<WPT> nj = ld<WPT>(nb, v);
-  Elem<WPT> xu[K], xv[K];
-#pragma unroll
-  for (int q = 0; q < K; ++q) {
-    xu[q] = ld<WPT>(nb, iu[q]);
-    xv[q] = ld<WPT>(nb, iv[q]);
-  }
-  u64 r[WPT];
-  accept_words<WPT>(t, c, (uint32_t)E.z, plane, k0, k1, noise, r);
-  u64 d[WPT];
-  exchange<K, WPT>(ni, nj, xu, xv, r, m, d);
-  u64 any = 0;
-#pragma unroll
-  for (int w = 0; w < WPT; ++w) any |= d[w];
-  if (any) {
-    st<WPT>(nb, u, ni);
-    st<WPT>(nb, v, nj);
-    Elem<WPT> fu = ld<WPT>(fb, u);
-    Elem<WPT> fv = ld<WPT>(fb, v);
-    u64 new_u = 0, new_v = 0;
-#pragma unroll
-    for (int w = 0; w < WPT; ++w) {
-      new_u |= d[w] & ~fu.w[w];
-      new_v |= d[w] & ~fv.w[w];
-      fu.w[w] |= d[w];
-      fv.w[w] |= d[w];
-    }
-    if (new_u) st<WPT>(fb, u, fu);
-    if (new_v) st<WPT>(fb, v, fv);
-  }
+  edge_update<K, WPT>(nb, fb, E.x, E.y, iu, iv, (uint32_t)E.z, plane, m, t, c, k0, k1, noise);
 }
 
 // ------------------------------------------------------------------------------------
