@@ -169,8 +169,14 @@ def run_batch_workload(args):
 
     shape = {}
 
+    # The members' initial states are built on a few streams of their own, so that the
+    # one-workgroup-per-replica-pair init kernels of different members run side by side;
+    # ka_batch_add orders each member's init before the batch's steps.
+    init_streams = [torch.cuda.Stream() for _ in range(4)]
+
     def batched(timed_kernel):
-        sims = [ka.ka_init(graphs[i["key"]], i["m"], i["rho"], i["seed"], i["R"], stream=stream) for i in man]
+        sims = [ka.ka_init(graphs[i["key"]], i["m"], i["rho"], i["seed"], i["R"],
+                           stream=init_streams[k % len(init_streams)]) for k, i in enumerate(man)]
         b = ka.ka_batch_create(len(sims), stream=stream)
         if shape:
             ka.ka_batch_set_option(b, ka.KA_BOPT_BLOCK, shape["block"])

@@ -1129,6 +1129,13 @@ int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out)
   return KA_OK;
 }
 
+void ka_sim_rebind_stream(ka_sim *s, hipStream_t stream)
+{
+  if (s->own_stream) (void)hipStreamDestroy(s->stream);
+  s->stream = stream;
+  s->own_stream = false;
+}
+
 // Bind the sim to a new stream that it owns (after waiting for its old one if asked to).
 int ka_sim_take_own_stream(ka_sim *s, bool wait)
 {

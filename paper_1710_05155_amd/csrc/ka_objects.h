@@ -89,4 +89,6 @@ int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out);
 // Move a sim onto a new stream that it owns (its old stream may then be destroyed).  With
 // wait = false the caller guarantees that no work of the sim is pending on the old stream.
 int ka_sim_take_own_stream(ka_sim *s, bool wait);
+// Bind the sim to `stream`, which the caller has already ordered after the sim's pending work.
+void ka_sim_rebind_stream(ka_sim *s, hipStream_t stream);
 

@@ -4,8 +4,9 @@
 //   1. takes newly submitted jobs into the FIFO queue;
 //   2. admits queue heads while a slot is free and their device footprint fits the budget
 //      (strict FIFO: a head that does not fit yet blocks the ones behind it, so big jobs
-//      are not starved): initial-state kernels, then the job joins the batch for the sweeps
-//      up to its next observation time;
+//      are not starved): initial-state kernels on a second stream, so that they overlap the
+//      batch steps already queued; the batch stream waits for them (an event), and the job
+//      joins the batch for the sweeps up to its next observation time;
 //   3. enqueues a chunk of batch steps, keeping at most two chunks in flight;
 //   4. detaches members whose segment completed, enqueues their observation (counts copied
 //      into pinned host memory) and either re-adds them for the next segment or marks them
@@ -80,6 +81,7 @@ struct ka_server {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  hipStream_t init_stream = nullptr;   // initial states of admitted jobs
   ka_batch *batch = nullptr;
   std::thread worker;
   std::mutex mu;
@@ -162,8 +164,18 @@ void admit(ka_server *sv)
     std::unique_ptr<Job> jp = std::move(sv->queue.front());
     sv->queue.pop_front();
     j->t_admit = Clock::now();
-    j->rc = ka_init(j->graph, j->m, j->rho, j->seed, j->R, sv->stream, &j->sim);
-    if (j->rc == KA_OK) sv->used += j->footprint;  // returned in retire() while j->sim is set
+    j->rc = ka_init(j->graph, j->m, j->rho, j->seed, j->R, sv->init_stream, &j->sim);
+    if (j->rc == KA_OK) {
+      sv->used += j->footprint;  // returned in retire() while j->sim is set
+      // everything after the init runs on the batch stream, ordered after it by an event
+      hipEvent_t ev = nullptr;
+      hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+      if (e == hipSuccess) e = hipEventRecord(ev, sv->init_stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(sv->stream, ev, 0);
+      if (ev) (void)hipEventDestroy(ev);
+      if (e != hipSuccess) (void)hipStreamSynchronize(sv->init_stream);
+      ka_sim_rebind_stream(j->sim, sv->stream);
+    }
     if (j->rc == KA_OK && hipHostMalloc((void **)&j->pinned, j->obs.size() * 3u * (size_t)j->R *
                                                                   sizeof(unsigned long long),
                                         hipHostMallocDefault) != hipSuccess)
@@ -321,8 +333,15 @@ extern "C" int ka_server_create(size_t device_budget, int max_active, void *hip_
     delete sv;
     return sfail(KA_EDEVICE, "stream: %s", hipGetErrorString(e));
   }
+  e = hipStreamCreate(&sv->init_stream);
+  if (e != hipSuccess) {
+    if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
+    delete sv;
+    return sfail(KA_EDEVICE, "stream: %s", hipGetErrorString(e));
+  }
   int rc = ka_batch_create(max_active, sv->stream, &sv->batch);
   if (rc != KA_OK) {
+    (void)hipStreamDestroy(sv->init_stream);
     if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
     delete sv;
     return rc;
@@ -494,6 +513,8 @@ extern "C" void ka_server_free(ka_server *sv)
     if (j->pinned) (void)hipHostFree(j->pinned);
     if (j->done_ev) (void)hipEventDestroy(j->done_ev);
   }
+  (void)hipStreamSynchronize(sv->init_stream);
+  (void)hipStreamDestroy(sv->init_stream);
   if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
   delete sv;
 }
