@@ -333,219 +333,238 @@ void harvest(ka_batch *b)
 
 extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
 {
-  if (!out) return bfail(KA_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (capacity < 1 || capacity > ka::kBatchMaxMembers)
-    return bfail(KA_EINVAL, "capacity must be in [1, %d]", ka::kBatchMaxMembers);
-  ka_batch *b = new (std::nothrow) ka_batch;
-  if (!b) return bfail(KA_ENOMEM, "host allocation failed");
-  (void)hipGetDevice(&b->device);
-  int cus = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
-    b->cus = cus;
-  b->capacity = capacity;
-  b->sims.assign((size_t)capacity, nullptr);
-  b->sweeps.assign((size_t)capacity, 0);
-  b->class_sizes.assign((size_t)capacity, std::vector<int>());
-  hipError_t e = hipSuccess;
-  if (hip_stream) {
-    b->stream = (hipStream_t)hip_stream;
-  } else {
-    e = hipStreamCreate(&b->stream);
-    b->own_stream = e == hipSuccess;
-  }
-  if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_tab, sizeof(ka::BatchMember) * (size_t)capacity, hipHostMallocDefault);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_tab, sizeof(ka::BatchMember) * (size_t)capacity);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_base, sizeof(long long));
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_total, sizeof(int));
-  if (e == hipSuccess) {
-    std::memset(b->host_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity);
-    e = hipMemsetAsync(b->d_base, 0, sizeof(long long), b->stream);
-  }
-  if (e == hipSuccess) e = hipMemsetAsync(b->d_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity, b->stream);
-  if (e != hipSuccess) {
-    if (b->host_tab) (void)hipHostFree(b->host_tab);
+  return ka_guard([&]() -> int {
+    if (!out) return bfail(KA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (capacity < 1 || capacity > ka::kBatchMaxMembers)
+      return bfail(KA_EINVAL, "capacity must be in [1, %d]", ka::kBatchMaxMembers);
+    ka_batch *b = new (std::nothrow) ka_batch;
+    if (!b) return bfail(KA_ENOMEM, "host allocation failed");
+    (void)hipGetDevice(&b->device);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) == hipSuccess && cus > 0)
+      b->cus = cus;
+    b->capacity = capacity;
+    b->sims.assign((size_t)capacity, nullptr);
+    b->sweeps.assign((size_t)capacity, 0);
+    b->class_sizes.assign((size_t)capacity, std::vector<int>());
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+      b->stream = (hipStream_t)hip_stream;
+    } else {
+      e = hipStreamCreate(&b->stream);
+      b->own_stream = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_tab, sizeof(ka::BatchMember) * (size_t)capacity, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_tab, sizeof(ka::BatchMember) * (size_t)capacity);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_base, sizeof(long long));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->d_total, sizeof(int));
+    if (e == hipSuccess) {
+      std::memset(b->host_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity);
+      e = hipMemsetAsync(b->d_base, 0, sizeof(long long), b->stream);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity, b->stream);
+    if (e != hipSuccess) {
+      if (b->host_tab) (void)hipHostFree(b->host_tab);
+      (void)hipFree(b->d_tab);
+      (void)hipFree(b->d_base);
+      (void)hipFree(b->d_total);
+      if (b->own_stream) (void)hipStreamDestroy(b->stream);
+      delete b;
+      return bhip(e, "ka_batch_create");
+    }
+    b->dirty = true;
+    *out = b;
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
+{
+  return ka_guard([&]() -> int {
+    if (!b || !s) return bfail(KA_EINVAL, "NULL argument");
+    if (s->batch) return bfail(KA_ESTATE, "sim is already a batch member");
+    if (!s->n) return bfail(KA_ESTATE, "sim has no device state");
+    if (s->device != b->device) return bfail(KA_EINVAL, "sim and batch are on different devices");
+    if (n_sweeps < 0) return bfail(KA_EINVAL, "n_sweeps < 0");
+    if (s->t + n_sweeps >= (1ll << 32)) return bfail(KA_ESTATE, "sweep index would reach 2^32");
+    int k = 0;
+    while (k < b->capacity && b->sims[(size_t)k]) ++k;
+    if (k == b->capacity) return bfail(KA_ESTATE, "batch is full (%d members)", b->capacity);
+    Guard dg(b->device);
+    // order the member's own earlier work (init, sweeps) before the batch's steps
+    if (s->stream != b->stream) {
+      hipEvent_t ev = take_event(b);
+      hipError_t e = hipEventRecord(ev, s->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
+      b->event_pool.push_back(ev);
+      if (e != hipSuccess) return bhip(e, "ka_batch_add ordering");
+    }
+    ka::BatchMember m{};
+    m.n = s->n;
+    m.f = s->f;
+    m.edges = s->edges;
+    m.nbr = s->nbr;
+    m.stride = (long long)s->edges_total;
+    m.class_start = s->class_start_d;
+    m.kind = s->lattice ? 0 : 1;
+    m.d = s->geom.d;
+    m.L = s->geom.L;
+    m.Q = s->geom.Q;
+    m.P = s->geom.P;
+    m.qinv = s->geom.qinv;
+    m.N = (int)s->N;
+    m.z = s->z;
+    m.m = s->m;
+    m.C = s->C;
+    m.planes = s->planes;
+    m.wpt = s->wpt;
+    m.key0 = (uint32_t)s->seed;
+    m.key1 = (uint32_t)(s->seed >> 32);
+    m.noise = s->noise;
+    m.t0 = (uint32_t)s->t;
+    m.s_begin = b->step;
+    m.s_end = b->step + (int64_t)s->C * n_sweeps;
+    b->class_sizes[(size_t)k].clear();
+    if (!s->lattice)
+      for (int c = 0; c < s->C; ++c) b->class_sizes[(size_t)k].push_back(s->plan->class_start[(size_t)c + 1] - s->plan->class_start[(size_t)c]);
+    b->host_tab[k] = m;
+    b->sims[(size_t)k] = s;
+    b->sweeps[(size_t)k] = n_sweeps;
+    b->n_members = std::max(b->n_members, k + 1);
+    b->dirty = true;
+    s->batch = b;
+    if (slot) *slot = k;
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_batch_run(ka_batch *b, int64_t n_steps)
+{
+  return ka_guard([&]() -> int {
+    if (!b) return bfail(KA_EINVAL, "batch is NULL");
+    if (n_steps <= 0) return KA_OK;
+    Guard dg(b->device);
+    hipError_t e = hipSuccess;
+    if (b->autotune && !b->tuned) e = autotune(b, n_steps);
+    if (e == hipSuccess && n_steps > 0) e = enqueue_steps(b, n_steps);
+    if (e != hipSuccess) return bhip(e, "ka_batch_run");
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_batch_steps_left(const ka_batch *b, int64_t *steps_left)
+{
+  return ka_guard([&]() -> int {
+    if (!b || !steps_left) return bfail(KA_EINVAL, "NULL argument");
+    int64_t left = 0;
+    for (int k = 0; k < b->n_members; ++k)
+      if (b->sims[(size_t)k]) left = std::max<int64_t>(left, b->host_tab[k].s_end - b->step);
+    *steps_left = left;
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_batch_poll(ka_batch *b, int *slots, int max_slots, int *n_done)
+{
+  return ka_guard([&]() -> int {
+    if (!b) return bfail(KA_EINVAL, "batch is NULL");
+    Guard dg(b->device);
+    harvest(b);
+    int got = 0;
+    for (int k = 0; k < b->n_members; ++k) {
+      if (!b->sims[(size_t)k] || b->host_tab[k].s_end > b->done_step) continue;
+      if (slots && got >= max_slots) break;
+      detach(b, k);
+      if (slots) slots[got] = k;
+      ++got;
+    }
+    if (n_done) *n_done = got;
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_batch_wait_all(ka_batch *b)
+{
+  return ka_guard([&]() -> int {
+    if (!b) return bfail(KA_EINVAL, "batch is NULL");
+    int64_t left = 0;
+    ka_batch_steps_left(b, &left);
+    int rc = ka_batch_run(b, left);
+    if (rc) return rc;
+    Guard dg(b->device);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bhip(e, "ka_batch_wait_all");
+    harvest(b);
+    b->done_step = b->step;
+    for (int k = 0; k < b->n_members; ++k)
+      if (b->sims[(size_t)k]) detach(b, k);
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
+{
+  return ka_guard([&]() -> int {
+    if (!b) return bfail(KA_EINVAL, "batch is NULL");
+    switch (option) {
+      case KA_BOPT_AUTOTUNE:
+        b->autotune = value != 0;
+        return KA_OK;
+      case KA_BOPT_BLOCK:
+        if (value != 128 && value != 256 && value != 512) return bfail(KA_EINVAL, "block must be 128, 256 or 512");
+        if (b->block != (int)value) b->dirty = true;
+        b->block = (int)value;
+        b->autotune = false;
+        return KA_OK;
+      case KA_BOPT_GRAPH_STEPS:
+        if (value < 0 || value > 4096) return bfail(KA_EINVAL, "graph steps must be in [0, 4096]");
+        b->graph_steps = (int)value;
+        return KA_OK;
+      default:
+        return bfail(KA_EINVAL, "unknown batch option %d", option);
+    }
+  });
+}
+
+extern "C" int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *tiles)
+{
+  return ka_guard([&]() -> int {
+    if (!b) return bfail(KA_EINVAL, "batch is NULL");
+    int active = 0;
+    for (int k = 0; k < b->n_members; ++k) active += b->sims[(size_t)k] != nullptr;
+    if (step) *step = b->step;
+    if (members) *members = active;
+    if (block) *block = b->block;
+    if (tiles) *tiles = b->T[0] + b->T[1];
+    return KA_OK;
+  });
+}
+
+extern "C" void ka_batch_free(ka_batch *b)
+{
+  try {
+    if (!b) return;
+    (void)ka_batch_wait_all(b);
+    Guard dg(b->device);
+    (void)hipStreamSynchronize(b->stream);
+    drop_graph(b->graphs[0]);
+    drop_graph(b->graphs[1]);
+    for (auto &pr : b->progress) (void)hipEventDestroy(pr.first);
+    for (hipEvent_t ev : b->event_pool) (void)hipEventDestroy(ev);
+    for (int q = 0; q < 2; ++q)
+      for (int w = 0; w < 2; ++w) {
+        (void)hipFree(b->d_tmember[q][w]);
+        (void)hipFree(b->d_tlocal[q][w]);
+      }
+    (void)hipHostFree(b->host_tab);
     (void)hipFree(b->d_tab);
     (void)hipFree(b->d_base);
     (void)hipFree(b->d_total);
     if (b->own_stream) (void)hipStreamDestroy(b->stream);
     delete b;
-    return bhip(e, "ka_batch_create");
+  } catch (...) {
   }
-  b->dirty = true;
-  *out = b;
-  return KA_OK;
-}
-
-extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
-{
-  if (!b || !s) return bfail(KA_EINVAL, "NULL argument");
-  if (s->batch) return bfail(KA_ESTATE, "sim is already a batch member");
-  if (!s->n) return bfail(KA_ESTATE, "sim has no device state");
-  if (s->device != b->device) return bfail(KA_EINVAL, "sim and batch are on different devices");
-  if (n_sweeps < 0) return bfail(KA_EINVAL, "n_sweeps < 0");
-  if (s->t + n_sweeps >= (1ll << 32)) return bfail(KA_ESTATE, "sweep index would reach 2^32");
-  int k = 0;
-  while (k < b->capacity && b->sims[(size_t)k]) ++k;
-  if (k == b->capacity) return bfail(KA_ESTATE, "batch is full (%d members)", b->capacity);
-  Guard dg(b->device);
-  // order the member's own earlier work (init, sweeps) before the batch's steps
-  if (s->stream != b->stream) {
-    hipEvent_t ev = take_event(b);
-    hipError_t e = hipEventRecord(ev, s->stream);
-    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ev, 0);
-    b->event_pool.push_back(ev);
-    if (e != hipSuccess) return bhip(e, "ka_batch_add ordering");
-  }
-  ka::BatchMember m{};
-  m.n = s->n;
-  m.f = s->f;
-  m.edges = s->edges;
-  m.nbr = s->nbr;
-  m.stride = (long long)s->edges_total;
-  m.class_start = s->class_start_d;
-  m.kind = s->lattice ? 0 : 1;
-  m.d = s->geom.d;
-  m.L = s->geom.L;
-  m.Q = s->geom.Q;
-  m.P = s->geom.P;
-  m.qinv = s->geom.qinv;
-  m.N = (int)s->N;
-  m.z = s->z;
-  m.m = s->m;
-  m.C = s->C;
-  m.planes = s->planes;
-  m.wpt = s->wpt;
-  m.key0 = (uint32_t)s->seed;
-  m.key1 = (uint32_t)(s->seed >> 32);
-  m.noise = s->noise;
-  m.t0 = (uint32_t)s->t;
-  m.s_begin = b->step;
-  m.s_end = b->step + (int64_t)s->C * n_sweeps;
-  b->class_sizes[(size_t)k].clear();
-  if (!s->lattice)
-    for (int c = 0; c < s->C; ++c) b->class_sizes[(size_t)k].push_back(s->plan->class_start[(size_t)c + 1] - s->plan->class_start[(size_t)c]);
-  b->host_tab[k] = m;
-  b->sims[(size_t)k] = s;
-  b->sweeps[(size_t)k] = n_sweeps;
-  b->n_members = std::max(b->n_members, k + 1);
-  b->dirty = true;
-  s->batch = b;
-  if (slot) *slot = k;
-  return KA_OK;
-}
-
-extern "C" int ka_batch_run(ka_batch *b, int64_t n_steps)
-{
-  if (!b) return bfail(KA_EINVAL, "batch is NULL");
-  if (n_steps <= 0) return KA_OK;
-  Guard dg(b->device);
-  hipError_t e = hipSuccess;
-  if (b->autotune && !b->tuned) e = autotune(b, n_steps);
-  if (e == hipSuccess && n_steps > 0) e = enqueue_steps(b, n_steps);
-  if (e != hipSuccess) return bhip(e, "ka_batch_run");
-  return KA_OK;
-}
-
-extern "C" int ka_batch_steps_left(const ka_batch *b, int64_t *steps_left)
-{
-  if (!b || !steps_left) return bfail(KA_EINVAL, "NULL argument");
-  int64_t left = 0;
-  for (int k = 0; k < b->n_members; ++k)
-    if (b->sims[(size_t)k]) left = std::max<int64_t>(left, b->host_tab[k].s_end - b->step);
-  *steps_left = left;
-  return KA_OK;
-}
-
-extern "C" int ka_batch_poll(ka_batch *b, int *slots, int max_slots, int *n_done)
-{
-  if (!b) return bfail(KA_EINVAL, "batch is NULL");
-  Guard dg(b->device);
-  harvest(b);
-  int got = 0;
-  for (int k = 0; k < b->n_members; ++k) {
-    if (!b->sims[(size_t)k] || b->host_tab[k].s_end > b->done_step) continue;
-    if (slots && got >= max_slots) break;
-    detach(b, k);
-    if (slots) slots[got] = k;
-    ++got;
-  }
-  if (n_done) *n_done = got;
-  return KA_OK;
-}
-
-extern "C" int ka_batch_wait_all(ka_batch *b)
-{
-  if (!b) return bfail(KA_EINVAL, "batch is NULL");
-  int64_t left = 0;
-  ka_batch_steps_left(b, &left);
-  int rc = ka_batch_run(b, left);
-  if (rc) return rc;
-  Guard dg(b->device);
-  hipError_t e = hipStreamSynchronize(b->stream);
-  if (e != hipSuccess) return bhip(e, "ka_batch_wait_all");
-  harvest(b);
-  b->done_step = b->step;
-  for (int k = 0; k < b->n_members; ++k)
-    if (b->sims[(size_t)k]) detach(b, k);
-  return KA_OK;
-}
-
-extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
-{
-  if (!b) return bfail(KA_EINVAL, "batch is NULL");
-  switch (option) {
-    case KA_BOPT_AUTOTUNE:
-      b->autotune = value != 0;
-      return KA_OK;
-    case KA_BOPT_BLOCK:
-      if (value != 128 && value != 256 && value != 512) return bfail(KA_EINVAL, "block must be 128, 256 or 512");
-      if (b->block != (int)value) b->dirty = true;
-      b->block = (int)value;
-      b->autotune = false;
-      return KA_OK;
-    case KA_BOPT_GRAPH_STEPS:
-      if (value < 0 || value > 4096) return bfail(KA_EINVAL, "graph steps must be in [0, 4096]");
-      b->graph_steps = (int)value;
-      return KA_OK;
-    default:
-      return bfail(KA_EINVAL, "unknown batch option %d", option);
-  }
-}
-
-extern "C" int ka_batch_info(const ka_batch *b, int64_t *step, int *members, int *block, int *tiles)
-{
-  if (!b) return bfail(KA_EINVAL, "batch is NULL");
-  int active = 0;
-  for (int k = 0; k < b->n_members; ++k) active += b->sims[(size_t)k] != nullptr;
-  if (step) *step = b->step;
-  if (members) *members = active;
-  if (block) *block = b->block;
-  if (tiles) *tiles = b->T[0] + b->T[1];
-  return KA_OK;
-}
-
-extern "C" void ka_batch_free(ka_batch *b)
-{
-  if (!b) return;
-  (void)ka_batch_wait_all(b);
-  Guard dg(b->device);
-  (void)hipStreamSynchronize(b->stream);
-  drop_graph(b->graphs[0]);
-  drop_graph(b->graphs[1]);
-  for (auto &pr : b->progress) (void)hipEventDestroy(pr.first);
-  for (hipEvent_t ev : b->event_pool) (void)hipEventDestroy(ev);
-  for (int q = 0; q < 2; ++q)
-    for (int w = 0; w < 2; ++w) {
-      (void)hipFree(b->d_tmember[q][w]);
-      (void)hipFree(b->d_tlocal[q][w]);
-    }
-  (void)hipHostFree(b->host_tab);
-  (void)hipFree(b->d_tab);
-  (void)hipFree(b->d_base);
-  (void)hipFree(b->d_total);
-  if (b->own_stream) (void)hipStreamDestroy(b->stream);
-  delete b;
 }
 
 // Called by ka_free for a sim that is still a batch member.

@@ -192,25 +192,27 @@ int finish_general_graph(ka_graph &g)
 
 extern "C" int ka_graph_lattice(int d, int L, ka_graph **out)
 {
-  if (!out) return fail(KA_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (d != 2 && d != 3) return fail(KA_EINVAL, "lattice dimension must be 2 or 3 (got %d)", d);
-  if (L < 4 || L % 4 != 0) return fail(KA_EINVAL, "lattice side must be a multiple of 4, >= 4 (got %d)", L);
-  int64_t N = 1;
-  for (int k = 0; k < d; ++k) N *= L;
-  if (N > (1ll << 30)) return fail(KA_EINVAL, "lattice too large (N = %lld > 2^30)", (long long)N);
-  ka_graph *g = new (std::nothrow) ka_graph;
-  if (!g) return fail(KA_ENOMEM, "host allocation failed");
-  g->lattice = 1;
-  g->d = d;
-  g->L = L;
-  g->N = N;
-  g->z = 2 * d;
-  g->C = 4 * d;
-  // The explicit adjacency and edge lists of a lattice are written on export only: the
-  // kernels compute neighbours and classes from coordinates.
-  *out = g;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!out) return fail(KA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (d != 2 && d != 3) return fail(KA_EINVAL, "lattice dimension must be 2 or 3 (got %d)", d);
+    if (L < 4 || L % 4 != 0) return fail(KA_EINVAL, "lattice side must be a multiple of 4, >= 4 (got %d)", L);
+    int64_t N = 1;
+    for (int k = 0; k < d; ++k) N *= L;
+    if (N > (1ll << 30)) return fail(KA_EINVAL, "lattice too large (N = %lld > 2^30)", (long long)N);
+    ka_graph *g = new (std::nothrow) ka_graph;
+    if (!g) return fail(KA_ENOMEM, "host allocation failed");
+    g->lattice = 1;
+    g->d = d;
+    g->L = L;
+    g->N = N;
+    g->z = 2 * d;
+    g->C = 4 * d;
+    // The explicit adjacency and edge lists of a lattice are written on export only: the
+    // kernels compute neighbours and classes from coordinates.
+    *out = g;
+    return KA_OK;
+  });
 }
 
 namespace {
@@ -246,210 +248,220 @@ void lattice_export(const ka_graph *g, int32_t *adj, int32_t *eu, int32_t *ev, i
 
 extern "C" int ka_graph_rrg(int64_t N, int z, uint64_t graph_seed, ka_graph **out)
 {
-  if (!out) return fail(KA_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (z < 3 || z > 6) return fail(KA_EINVAL, "degree z must be in [3, 6] (got %d)", z);
-  if (N <= z || N > (1ll << 28) || (N * z) % 2 != 0)
-    return fail(KA_EINVAL, "need z < N <= 2^28 and N*z even (N = %lld, z = %d)", (long long)N, z);
-  ka_graph *g = new (std::nothrow) ka_graph;
-  if (!g) return fail(KA_ENOMEM, "host allocation failed");
-  g->N = N;
-  g->z = z;
-  const int64_t S = N * z;
-  std::vector<int32_t> stub, deg;
-  try {
-    stub.resize((size_t)S);
-    deg.resize((size_t)N);
-    g->adj.resize((size_t)S);
-  } catch (...) {
-    delete g;
-    return fail(KA_ENOMEM, "host allocation failed");
-  }
-  int32_t *adj = g->adj.data();
-  // Adds the edge (u, v) unless it is a self-loop or already present.
-  auto add_pair = [&](int32_t u, int32_t v) -> bool {
-    if (u == v) return false;
-    const int32_t *ru = adj + (size_t)u * z;
-    for (int k = 0; k < deg[u]; ++k)
-      if (ru[k] == v) return false;
-    adj[(size_t)u * z + deg[u]++] = v;
-    adj[(size_t)v * z + deg[v]++] = u;
-    return true;
-  };
-  bool found = false;
-  const int64_t max_attempts = 1000000;
-  for (int64_t a = 0; a < max_attempts && !found; ++a) {
-    WordStream ws(graph_seed, (uint32_t)a);
-    for (int64_t s = 0; s < S; ++s) stub[(size_t)s] = (int32_t)(s / z);
-    std::fill(deg.begin(), deg.end(), 0);
-    bool ok = true;
-    // Fisher-Yates from the top: after step k, positions k..S-1 are final, so the pair
-    // (2q, 2q+1) is known after step 2q and a bad pair ends the attempt early.  The
-    // attempt's random words do not depend on earlier attempts, so the accepted pairing
-    // is the same as with a complete shuffle followed by a check.
-    for (int64_t k = S - 1; k >= 1; --k) {
-      const int64_t j = ws.below((uint32_t)(k + 1));
-      std::swap(stub[(size_t)k], stub[(size_t)j]);
-      if ((k & 1) == 0 && !add_pair(stub[(size_t)k], stub[(size_t)k + 1])) {
-        ok = false;
-        break;
-      }
+  return ka_guard([&]() -> int {
+    if (!out) return fail(KA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (z < 3 || z > 6) return fail(KA_EINVAL, "degree z must be in [3, 6] (got %d)", z);
+    if (N <= z || N > (1ll << 28) || (N * z) % 2 != 0)
+      return fail(KA_EINVAL, "need z < N <= 2^28 and N*z even (N = %lld, z = %d)", (long long)N, z);
+    ka_graph *g = new (std::nothrow) ka_graph;
+    if (!g) return fail(KA_ENOMEM, "host allocation failed");
+    g->N = N;
+    g->z = z;
+    const int64_t S = N * z;
+    std::vector<int32_t> stub, deg;
+    try {
+      stub.resize((size_t)S);
+      deg.resize((size_t)N);
+      g->adj.resize((size_t)S);
+    } catch (...) {
+      delete g;
+      return fail(KA_ENOMEM, "host allocation failed");
     }
-    if (ok && !add_pair(stub[0], stub[1])) ok = false;
-    found = ok;
-  }
-  if (!found) {
-    delete g;
-    return fail(KA_ESTATE, "no simple pairing within %lld attempts", (long long)max_attempts);
-  }
-  for (int64_t i = 0; i < N; ++i) std::sort(adj + (size_t)i * z, adj + (size_t)i * z + z);
-  int rc = finish_general_graph(*g);
-  if (rc != KA_OK) {
-    delete g;
-    return rc;
-  }
-  *out = g;
-  return KA_OK;
+    int32_t *adj = g->adj.data();
+    // Adds the edge (u, v) unless it is a self-loop or already present.
+    auto add_pair = [&](int32_t u, int32_t v) -> bool {
+      if (u == v) return false;
+      const int32_t *ru = adj + (size_t)u * z;
+      for (int k = 0; k < deg[u]; ++k)
+        if (ru[k] == v) return false;
+      adj[(size_t)u * z + deg[u]++] = v;
+      adj[(size_t)v * z + deg[v]++] = u;
+      return true;
+    };
+    bool found = false;
+    const int64_t max_attempts = 1000000;
+    for (int64_t a = 0; a < max_attempts && !found; ++a) {
+      WordStream ws(graph_seed, (uint32_t)a);
+      for (int64_t s = 0; s < S; ++s) stub[(size_t)s] = (int32_t)(s / z);
+      std::fill(deg.begin(), deg.end(), 0);
+      bool ok = true;
+      // Fisher-Yates from the top: after step k, positions k..S-1 are final, so the pair
+      // (2q, 2q+1) is known after step 2q and a bad pair ends the attempt early.  The
+      // attempt's random words do not depend on earlier attempts, so the accepted pairing
+      // is the same as with a complete shuffle followed by a check.
+      for (int64_t k = S - 1; k >= 1; --k) {
+        const int64_t j = ws.below((uint32_t)(k + 1));
+        std::swap(stub[(size_t)k], stub[(size_t)j]);
+        if ((k & 1) == 0 && !add_pair(stub[(size_t)k], stub[(size_t)k + 1])) {
+          ok = false;
+          break;
+        }
+      }
+      if (ok && !add_pair(stub[0], stub[1])) ok = false;
+      found = ok;
+    }
+    if (!found) {
+      delete g;
+      return fail(KA_ESTATE, "no simple pairing within %lld attempts", (long long)max_attempts);
+    }
+    for (int64_t i = 0; i < N; ++i) std::sort(adj + (size_t)i * z, adj + (size_t)i * z + z);
+    int rc = finish_general_graph(*g);
+    if (rc != KA_OK) {
+      delete g;
+      return rc;
+    }
+    *out = g;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_graph_layered(int d, int L, int M, uint64_t graph_seed, ka_graph **out)
 {
-  if (!out) return fail(KA_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (d != 2 && d != 3) return fail(KA_EINVAL, "lattice dimension must be 2 or 3 (got %d)", d);
-  if (L < 3) return fail(KA_EINVAL, "lattice side must be >= 3 (got %d)", L);
-  if (M < 1) return fail(KA_EINVAL, "number of copies must be >= 1 (got %d)", M);
-  int64_t Nb = 1;
-  for (int k = 0; k < d; ++k) Nb *= L;
-  if (Nb * M > (1ll << 28)) return fail(KA_EINVAL, "layered graph too large (%lld sites)", (long long)(Nb * M));
-  ka_graph *g = new (std::nothrow) ka_graph;
-  if (!g) return fail(KA_ENOMEM, "host allocation failed");
-  const int z = 2 * d;
-  g->N = Nb * M;
-  g->z = z;
-  try {
-    g->adj.resize((size_t)g->N * z);
-  } catch (...) {
-    delete g;
-    return fail(KA_ENOMEM, "host allocation failed");
-  }
-  const int64_t stride[3] = {1, L, (int64_t)L * L};
-  std::vector<int> fill((size_t)g->N, 0);
-  std::vector<int32_t> perm((size_t)M);
-  for (int64_t i = 0; i < Nb; ++i) {
-    for (int mu = 0; mu < d; ++mu) {
-      const int x_mu = (int)((i / stride[mu]) % L);
-      const int64_t j = i + (x_mu + 1 < L ? stride[mu] : -(int64_t)(L - 1) * stride[mu]);
-      // permutation of the M copies for this bond (base edge id i*d + mu)
-      const uint64_t e = (uint64_t)(i * d + mu);
-      uint32_t words[4];
-      uint64_t next = 0, block = UINT64_MAX;
-      auto word = [&]() -> uint32_t {
-        const uint64_t q = next / 4;
-        if (q != block) {
-          const uint32_t ctr[4] = {(uint32_t)e, 0xFFFFFFFDu, (uint32_t)q, 0u};
-          philox_host(ctr, graph_seed, words);
-          block = q;
-        }
-        return words[next++ % 4];
-      };
-      auto below = [&](uint32_t range) -> uint32_t {  // Lemire's multiply-shift with rejection
-        uint64_t prod = (uint64_t)word() * range;
-        uint32_t low = (uint32_t)prod;
-        if (low < range) {
-          const uint32_t thresh = (uint32_t)(0u - range) % range;
-          while (low < thresh) {
-            prod = (uint64_t)word() * range;
-            low = (uint32_t)prod;
+  return ka_guard([&]() -> int {
+    if (!out) return fail(KA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (d != 2 && d != 3) return fail(KA_EINVAL, "lattice dimension must be 2 or 3 (got %d)", d);
+    if (L < 3) return fail(KA_EINVAL, "lattice side must be >= 3 (got %d)", L);
+    if (M < 1) return fail(KA_EINVAL, "number of copies must be >= 1 (got %d)", M);
+    int64_t Nb = 1;
+    for (int k = 0; k < d; ++k) Nb *= L;
+    if (Nb * M > (1ll << 28)) return fail(KA_EINVAL, "layered graph too large (%lld sites)", (long long)(Nb * M));
+    ka_graph *g = new (std::nothrow) ka_graph;
+    if (!g) return fail(KA_ENOMEM, "host allocation failed");
+    const int z = 2 * d;
+    g->N = Nb * M;
+    g->z = z;
+    try {
+      g->adj.resize((size_t)g->N * z);
+    } catch (...) {
+      delete g;
+      return fail(KA_ENOMEM, "host allocation failed");
+    }
+    const int64_t stride[3] = {1, L, (int64_t)L * L};
+    std::vector<int> fill((size_t)g->N, 0);
+    std::vector<int32_t> perm((size_t)M);
+    for (int64_t i = 0; i < Nb; ++i) {
+      for (int mu = 0; mu < d; ++mu) {
+        const int x_mu = (int)((i / stride[mu]) % L);
+        const int64_t j = i + (x_mu + 1 < L ? stride[mu] : -(int64_t)(L - 1) * stride[mu]);
+        // permutation of the M copies for this bond (base edge id i*d + mu)
+        const uint64_t e = (uint64_t)(i * d + mu);
+        uint32_t words[4];
+        uint64_t next = 0, block = UINT64_MAX;
+        auto word = [&]() -> uint32_t {
+          const uint64_t q = next / 4;
+          if (q != block) {
+            const uint32_t ctr[4] = {(uint32_t)e, 0xFFFFFFFDu, (uint32_t)q, 0u};
+            philox_host(ctr, graph_seed, words);
+            block = q;
           }
+          return words[next++ % 4];
+        };
+        auto below = [&](uint32_t range) -> uint32_t {  // Lemire's multiply-shift with rejection
+          uint64_t prod = (uint64_t)word() * range;
+          uint32_t low = (uint32_t)prod;
+          if (low < range) {
+            const uint32_t thresh = (uint32_t)(0u - range) % range;
+            while (low < thresh) {
+              prod = (uint64_t)word() * range;
+              low = (uint32_t)prod;
+            }
+          }
+          return (uint32_t)(prod >> 32);
+        };
+        for (int a = 0; a < M; ++a) perm[(size_t)a] = a;
+        for (int k = M - 1; k >= 1; --k) std::swap(perm[(size_t)k], perm[below((uint32_t)(k + 1))]);
+        for (int a = 0; a < M; ++a) {
+          const int64_t u = (int64_t)a * Nb + i, v = (int64_t)perm[(size_t)a] * Nb + j;
+          g->adj[(size_t)u * z + fill[(size_t)u]++] = (int32_t)v;
+          g->adj[(size_t)v * z + fill[(size_t)v]++] = (int32_t)u;
         }
-        return (uint32_t)(prod >> 32);
-      };
-      for (int a = 0; a < M; ++a) perm[(size_t)a] = a;
-      for (int k = M - 1; k >= 1; --k) std::swap(perm[(size_t)k], perm[below((uint32_t)(k + 1))]);
-      for (int a = 0; a < M; ++a) {
-        const int64_t u = (int64_t)a * Nb + i, v = (int64_t)perm[(size_t)a] * Nb + j;
-        g->adj[(size_t)u * z + fill[(size_t)u]++] = (int32_t)v;
-        g->adj[(size_t)v * z + fill[(size_t)v]++] = (int32_t)u;
       }
     }
-  }
-  for (int64_t v = 0; v < g->N; ++v) std::sort(&g->adj[(size_t)v * z], &g->adj[(size_t)v * z] + z);
-  int rc = finish_general_graph(*g);
-  if (rc != KA_OK) {
-    delete g;
-    return rc;
-  }
-  if (L % 4 == 0) {
-    // Classes by projection to the lattice: an edge takes the class of the bond it lifts.
-    // Projection maps edges to edges, so distances can only shrink under it; two lifts of
-    // one bond share no site and no link.  The lattice classes therefore stay valid.
-    for (size_t q = 0; q < g->eu.size(); ++q) {
-      const int64_t iu = g->eu[q] % Nb, iv = g->ev[q] % Nb;
-      int mu = 0;
-      for (int k = 0; k < d; ++k)
-        if ((iu / stride[k]) % L != (iv / stride[k]) % L) mu = k;
-      const int64_t xu = (iu / stride[mu]) % L;
-      const int64_t lo = ((xu + 1) % L == (iv / stride[mu]) % L) ? iu : iv;
-      int others = 0;
-      for (int k = 0; k < d; ++k)
-        if (k != mu) others += (int)((lo / stride[k]) % L);
-      g->ecls[q] = 4 * mu + (int)((((lo / stride[mu]) % L) + 2 * others) & 3);
+    for (int64_t v = 0; v < g->N; ++v) std::sort(&g->adj[(size_t)v * z], &g->adj[(size_t)v * z] + z);
+    int rc = finish_general_graph(*g);
+    if (rc != KA_OK) {
+      delete g;
+      return rc;
     }
-    g->C = 4 * d;
-  }
-  *out = g;
-  return KA_OK;
+    if (L % 4 == 0) {
+      // Classes by projection to the lattice: an edge takes the class of the bond it lifts.
+      // Projection maps edges to edges, so distances can only shrink under it; two lifts of
+      // one bond share no site and no link.  The lattice classes therefore stay valid.
+      for (size_t q = 0; q < g->eu.size(); ++q) {
+        const int64_t iu = g->eu[q] % Nb, iv = g->ev[q] % Nb;
+        int mu = 0;
+        for (int k = 0; k < d; ++k)
+          if ((iu / stride[k]) % L != (iv / stride[k]) % L) mu = k;
+        const int64_t xu = (iu / stride[mu]) % L;
+        const int64_t lo = ((xu + 1) % L == (iv / stride[mu]) % L) ? iu : iv;
+        int others = 0;
+        for (int k = 0; k < d; ++k)
+          if (k != mu) others += (int)((lo / stride[k]) % L);
+        g->ecls[q] = 4 * mu + (int)((((lo / stride[mu]) % L) + 2 * others) & 3);
+      }
+      g->C = 4 * d;
+    }
+    *out = g;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_graph_from_adjacency(int64_t N, int z, const int32_t *adj, ka_graph **out)
 {
-  if (!out || !adj) return fail(KA_EINVAL, "NULL argument");
-  *out = nullptr;
-  if (z < 3 || z > 6) return fail(KA_EINVAL, "degree z must be in [3, 6] (got %d)", z);
-  if (N <= z || N > (1ll << 28)) return fail(KA_EINVAL, "need z < N <= 2^28 (N = %lld)", (long long)N);
-  ka_graph *g = new (std::nothrow) ka_graph;
-  if (!g) return fail(KA_ENOMEM, "host allocation failed");
-  g->N = N;
-  g->z = z;
-  try {
-    g->adj.assign(adj, adj + (size_t)N * z);
-  } catch (...) {
-    delete g;
-    return fail(KA_ENOMEM, "host allocation failed");
-  }
-  int rc = finish_general_graph(*g);
-  if (rc != KA_OK) {
-    delete g;
-    return rc;
-  }
-  *out = g;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!out || !adj) return fail(KA_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (z < 3 || z > 6) return fail(KA_EINVAL, "degree z must be in [3, 6] (got %d)", z);
+    if (N <= z || N > (1ll << 28)) return fail(KA_EINVAL, "need z < N <= 2^28 (N = %lld)", (long long)N);
+    ka_graph *g = new (std::nothrow) ka_graph;
+    if (!g) return fail(KA_ENOMEM, "host allocation failed");
+    g->N = N;
+    g->z = z;
+    try {
+      g->adj.assign(adj, adj + (size_t)N * z);
+    } catch (...) {
+      delete g;
+      return fail(KA_ENOMEM, "host allocation failed");
+    }
+    int rc = finish_general_graph(*g);
+    if (rc != KA_OK) {
+      delete g;
+      return rc;
+    }
+    *out = g;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_graph_info(const ka_graph *g, int64_t *N, int *z, int64_t *n_edges, int *n_classes)
 {
-  if (!g) return fail(KA_EINVAL, "graph is NULL");
-  if (N) *N = g->N;
-  if (z) *z = g->z;
-  if (n_edges) *n_edges = g->lattice ? g->N * g->d : (int64_t)g->eu.size();
-  if (n_classes) *n_classes = g->C;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!g) return fail(KA_EINVAL, "graph is NULL");
+    if (N) *N = g->N;
+    if (z) *z = g->z;
+    if (n_edges) *n_edges = g->lattice ? g->N * g->d : (int64_t)g->eu.size();
+    if (n_classes) *n_classes = g->C;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_graph_export(const ka_graph *g, int32_t *adj, int32_t *edge_u, int32_t *edge_v,
                                int32_t *edge_class)
 {
-  if (!g) return fail(KA_EINVAL, "graph is NULL");
-  if (g->lattice) {
-    lattice_export(g, adj, edge_u, edge_v, edge_class);
+  return ka_guard([&]() -> int {
+    if (!g) return fail(KA_EINVAL, "graph is NULL");
+    if (g->lattice) {
+      lattice_export(g, adj, edge_u, edge_v, edge_class);
+      return KA_OK;
+    }
+    if (adj) std::memcpy(adj, g->adj.data(), g->adj.size() * sizeof(int32_t));
+    if (edge_u) std::memcpy(edge_u, g->eu.data(), g->eu.size() * sizeof(int32_t));
+    if (edge_v) std::memcpy(edge_v, g->ev.data(), g->ev.size() * sizeof(int32_t));
+    if (edge_class) std::memcpy(edge_class, g->ecls.data(), g->ecls.size() * sizeof(int32_t));
     return KA_OK;
-  }
-  if (adj) std::memcpy(adj, g->adj.data(), g->adj.size() * sizeof(int32_t));
-  if (edge_u) std::memcpy(edge_u, g->eu.data(), g->eu.size() * sizeof(int32_t));
-  if (edge_v) std::memcpy(edge_v, g->ev.data(), g->ev.size() * sizeof(int32_t));
-  if (edge_class) std::memcpy(edge_class, g->ecls.data(), g->ecls.size() * sizeof(int32_t));
-  return KA_OK;
+  });
 }
 
 extern "C" void ka_graph_free(ka_graph *g) { delete g; }
@@ -883,234 +895,246 @@ int check_sim(const ka_sim *s)
 
 extern "C" int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_bytes)
 {
-  if (!g || !device_bytes) return fail(KA_EINVAL, "NULL argument");
-  if (n_replicas <= 0 || n_replicas % 64 != 0) return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
-  *device_bytes = state_bytes(g->N, n_replicas) + graph_device_bytes(g) +
-                  (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!g || !device_bytes) return fail(KA_EINVAL, "NULL argument");
+    if (n_replicas <= 0 || n_replicas % 64 != 0) return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
+    *device_bytes = state_bytes(g->N, n_replicas) + graph_device_bytes(g) +
+                    (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int n_replicas,
                          void *hip_stream, ka_sim **out)
 {
-  if (!out) return fail(KA_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (!g) return fail(KA_EINVAL, "graph is NULL");
-  if (m < 0 || m > g->z - 1) return fail(KA_EINVAL, "activation number m must be in [0, z-1] = [0, %d] (got %d)", g->z - 1, m);
-  if (n_replicas <= 0 || n_replicas % 64 != 0)
-    return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64 (got %d)", n_replicas);
-  if (K < 0 || K > g->N) return fail(KA_EINVAL, "particle number K must be in [0, N] (got %lld)", (long long)K);
-  ka_sim *s = new (std::nothrow) ka_sim;
-  if (!s) return fail(KA_ENOMEM, "host allocation failed");
-  s->lattice = g->lattice;
-  s->z = g->z;
-  s->C = g->C;
-  s->N = g->N;
-  s->m = m;
-  s->K = K;
-  s->seed = seed;
-  s->R = n_replicas;
-  s->W = n_replicas / 64;
-  s->wpt = (s->W % 2 == 0) ? 2 : 1;
-  s->planes = s->W / s->wpt;
-  (void)hipGetDevice(&s->device);
-  if (hip_stream) {
-    s->stream = (hipStream_t)hip_stream;
-  } else {
-    hipError_t e = hipStreamCreate(&s->stream);
-    if (e != hipSuccess) {
-      delete s;
-      return hip_fail(e, "hipStreamCreate");
+  return ka_guard([&]() -> int {
+    if (!out) return fail(KA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail(KA_EINVAL, "graph is NULL");
+    if (m < 0 || m > g->z - 1) return fail(KA_EINVAL, "activation number m must be in [0, z-1] = [0, %d] (got %d)", g->z - 1, m);
+    if (n_replicas <= 0 || n_replicas % 64 != 0)
+      return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64 (got %d)", n_replicas);
+    if (K < 0 || K > g->N) return fail(KA_EINVAL, "particle number K must be in [0, N] (got %lld)", (long long)K);
+    ka_sim *s = new (std::nothrow) ka_sim;
+    if (!s) return fail(KA_ENOMEM, "host allocation failed");
+    s->lattice = g->lattice;
+    s->z = g->z;
+    s->C = g->C;
+    s->N = g->N;
+    s->m = m;
+    s->K = K;
+    s->seed = seed;
+    s->R = n_replicas;
+    s->W = n_replicas / 64;
+    s->wpt = (s->W % 2 == 0) ? 2 : 1;
+    s->planes = s->W / s->wpt;
+    (void)hipGetDevice(&s->device);
+    if (hip_stream) {
+      s->stream = (hipStream_t)hip_stream;
+    } else {
+      hipError_t e = hipStreamCreate(&s->stream);
+      if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "hipStreamCreate");
+      }
+      s->own_stream = true;
     }
-    s->own_stream = true;
-  }
-  const size_t words = (size_t)s->N * s->W;
-  hipError_t e = hipSuccess;
-  if (e == hipSuccess) e = dalloc(&s->n, words * 8);
-  if (e == hipSuccess) e = dalloc(&s->n0, words * 8);
-  if (e == hipSuccess) e = dalloc(&s->f, words * 8);
-  if (e == hipSuccess) e = dalloc(&s->thr_u, (size_t)s->R * 8);
-  if (e == hipSuccess) e = dalloc(&s->thr_i, (size_t)s->R * 8);
-  if (e == hipSuccess) e = dalloc(&s->err, sizeof(int));
-  if (e != hipSuccess) {
-    free_device(s);
-    if (s->own_stream) (void)hipStreamDestroy(s->stream);
-    delete s;
-    return fail(KA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
-  }
-  if (s->lattice) {
-    s->geom.d = g->d;
-    s->geom.L = g->L;
-    s->geom.Q = g->L / 4;
-    s->geom.P = g->d == 2 ? s->geom.Q * s->geom.Q : s->geom.Q * s->geom.Q * s->geom.Q;
-    s->geom.N = (int)g->N;
-    s->geom.qinv = ka::lattice_qinv(s->geom.Q);
-  } else {
-    const std::shared_ptr<const GraphPlan> plan = graph_plan(g);
-    if (!plan) {
-      free_device(s);
-      if (s->own_stream) (void)hipStreamDestroy(s->stream);
-      delete s;
-      return fail(KA_ENOMEM, "host allocation failed for the graph schedule");
-    }
-    // The sim keeps the plan alive, so the copies below may run after the graph is freed.
-    s->plan = plan;
-    const std::vector<int32_t> &site_of = plan->site_of;
-    const std::vector<int4> &rec = plan->rec;
-    const std::vector<int32_t> &nbr = plan->nbr;
-    const std::vector<int> &cs = plan->class_start;
-    s->edges_total = rec.size();
-    e = dalloc(&s->nbr, nbr.size() * 4);
-    if (e == hipSuccess) e = dalloc(&s->site_of, site_of.size() * sizeof(int32_t));
-    if (e == hipSuccess) e = dalloc(&s->edges, rec.size() * sizeof(int4));
-    if (e == hipSuccess) e = dalloc(&s->class_start_d, cs.size() * sizeof(int));
-    if (e == hipSuccess) e = hipMemcpyAsync(s->nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->site_of, site_of.data(), site_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(s->class_start_d, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice, s->stream);
+    const size_t words = (size_t)s->N * s->W;
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = dalloc(&s->n, words * 8);
+    if (e == hipSuccess) e = dalloc(&s->n0, words * 8);
+    if (e == hipSuccess) e = dalloc(&s->f, words * 8);
+    if (e == hipSuccess) e = dalloc(&s->thr_u, (size_t)s->R * 8);
+    if (e == hipSuccess) e = dalloc(&s->thr_i, (size_t)s->R * 8);
+    if (e == hipSuccess) e = dalloc(&s->err, sizeof(int));
     if (e != hipSuccess) {
       free_device(s);
       if (s->own_stream) (void)hipStreamDestroy(s->stream);
       delete s;
-      return fail(KA_ENOMEM, "device allocation/copy failed: %s", hipGetErrorString(e));
+      return fail(KA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
     }
-  }
-  s->lds_bytes = ka::sweep_lds_bytes((int)s->N, s->wpt);
-  s->lds_fits = s->lds_bytes + 4096 <= (size_t)ka::max_lds_bytes();
-  // initial state
-  ka::InitArgs a{};
-  a.N = (int)s->N;
-  a.K = K;
-  a.key0 = (uint32_t)seed;
-  a.key1 = (uint32_t)(seed >> 32);
-  a.thr_u = s->thr_u;
-  a.thr_i = s->thr_i;
-  a.err = s->err;
-  a.n = s->n;
-  a.n0 = s->n0;
-  a.f = s->f;
-  a.planes = s->planes;
-  a.is_lattice = s->lattice;
-  a.g = s->geom;
-  a.site_of = s->site_of;
-  e = hipMemsetAsync(s->err, 0, sizeof(int), s->stream);
-  if (e == hipSuccess) e = ka::launch_init(a, s->R, s->wpt, s->stream);
-  if (e != hipSuccess) {
-    free_device(s);
-    if (s->own_stream) (void)hipStreamDestroy(s->stream);
-    delete s;
-    return hip_fail(e, "init kernels");
-  }
-  *out = s;
-  return KA_OK;
+    if (s->lattice) {
+      s->geom.d = g->d;
+      s->geom.L = g->L;
+      s->geom.Q = g->L / 4;
+      s->geom.P = g->d == 2 ? s->geom.Q * s->geom.Q : s->geom.Q * s->geom.Q * s->geom.Q;
+      s->geom.N = (int)g->N;
+      s->geom.qinv = ka::lattice_qinv(s->geom.Q);
+    } else {
+      const std::shared_ptr<const GraphPlan> plan = graph_plan(g);
+      if (!plan) {
+        free_device(s);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return fail(KA_ENOMEM, "host allocation failed for the graph schedule");
+      }
+      // The sim keeps the plan alive, so the copies below may run after the graph is freed.
+      s->plan = plan;
+      const std::vector<int32_t> &site_of = plan->site_of;
+      const std::vector<int4> &rec = plan->rec;
+      const std::vector<int32_t> &nbr = plan->nbr;
+      const std::vector<int> &cs = plan->class_start;
+      s->edges_total = rec.size();
+      e = dalloc(&s->nbr, nbr.size() * 4);
+      if (e == hipSuccess) e = dalloc(&s->site_of, site_of.size() * sizeof(int32_t));
+      if (e == hipSuccess) e = dalloc(&s->edges, rec.size() * sizeof(int4));
+      if (e == hipSuccess) e = dalloc(&s->class_start_d, cs.size() * sizeof(int));
+      if (e == hipSuccess) e = hipMemcpyAsync(s->nbr, nbr.data(), nbr.size() * 4, hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->site_of, site_of.data(), site_of.size() * sizeof(int32_t), hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(s->class_start_d, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice, s->stream);
+      if (e != hipSuccess) {
+        free_device(s);
+        if (s->own_stream) (void)hipStreamDestroy(s->stream);
+        delete s;
+        return fail(KA_ENOMEM, "device allocation/copy failed: %s", hipGetErrorString(e));
+      }
+    }
+    s->lds_bytes = ka::sweep_lds_bytes((int)s->N, s->wpt);
+    s->lds_fits = s->lds_bytes + 4096 <= (size_t)ka::max_lds_bytes();
+    // initial state
+    ka::InitArgs a{};
+    a.N = (int)s->N;
+    a.K = K;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.thr_u = s->thr_u;
+    a.thr_i = s->thr_i;
+    a.err = s->err;
+    a.n = s->n;
+    a.n0 = s->n0;
+    a.f = s->f;
+    a.planes = s->planes;
+    a.is_lattice = s->lattice;
+    a.g = s->geom;
+    a.site_of = s->site_of;
+    e = hipMemsetAsync(s->err, 0, sizeof(int), s->stream);
+    if (e == hipSuccess) e = ka::launch_init(a, s->R, s->wpt, s->stream);
+    if (e != hipSuccess) {
+      free_device(s);
+      if (s->own_stream) (void)hipStreamDestroy(s->stream);
+      delete s;
+      return hip_fail(e, "init kernels");
+    }
+    *out = s;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_init(const ka_graph *g, int m, double rho, uint64_t seed, int n_replicas,
                        void *hip_stream, ka_sim **out)
 {
-  if (!g) return fail(KA_EINVAL, "graph is NULL");
-  if (!(rho >= 0.0 && rho <= 1.0)) return fail(KA_EINVAL, "density rho must be in [0, 1]");
-  const int64_t K = (int64_t)std::floor(rho * (double)g->N + 0.5);
-  return ka_init_k(g, m, K, seed, n_replicas, hip_stream, out);
+  return ka_guard([&]() -> int {
+    if (!g) return fail(KA_EINVAL, "graph is NULL");
+    if (!(rho >= 0.0 && rho <= 1.0)) return fail(KA_EINVAL, "density rho must be in [0, 1]");
+    const int64_t K = (int64_t)std::floor(rho * (double)g->N + 0.5);
+    return ka_init_k(g, m, K, seed, n_replicas, hip_stream, out);
+  });
 }
 
 extern "C" int ka_sweep(ka_sim *s, int64_t n_sweeps)
 {
-  int rc = check_sim(s);
-  if (rc) return rc;
-  if (n_sweeps < 0) return fail(KA_EINVAL, "n_sweeps < 0");
-  if (s->t + n_sweeps >= (1ll << 32)) return fail(KA_ESTATE, "sweep index would reach 2^32");
-  DeviceGuard dg(s->device);
-  hipError_t e = hipSuccess;
-  if (use_lds(s)) {
-    int64_t done = 0;
-    while (done < n_sweeps && e == hipSuccess) {
-      const int64_t chunk = std::min(kLdsChunk, n_sweeps - done);
-      e = ensure_obs_buffers(s, 1);
-      if (e == hipSuccess) e = launch_lds(s, s->t + done, s->t + done + chunk, 0, 0);
-      done += chunk;
+  return ka_guard([&]() -> int {
+    int rc = check_sim(s);
+    if (rc) return rc;
+    if (n_sweeps < 0) return fail(KA_EINVAL, "n_sweeps < 0");
+    if (s->t + n_sweeps >= (1ll << 32)) return fail(KA_ESTATE, "sweep index would reach 2^32");
+    DeviceGuard dg(s->device);
+    hipError_t e = hipSuccess;
+    if (use_lds(s)) {
+      int64_t done = 0;
+      while (done < n_sweeps && e == hipSuccess) {
+        const int64_t chunk = std::min(kLdsChunk, n_sweeps - done);
+        e = ensure_obs_buffers(s, 1);
+        if (e == hipSuccess) e = launch_lds(s, s->t + done, s->t + done + chunk, 0, 0);
+        done += chunk;
+      }
+    } else {
+      e = sweep_global(s, n_sweeps);
     }
-  } else {
-    e = sweep_global(s, n_sweeps);
-  }
-  if (e != hipSuccess) return hip_fail(e, "ka_sweep");
-  s->t += n_sweeps;
-  return KA_OK;
+    if (e != hipSuccess) return hip_fail(e, "ka_sweep");
+    s->t += n_sweeps;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_run(ka_sim *s, const int64_t *obs_times, int n_obs, int64_t *density,
                       int64_t *overlap, int64_t *persistence)
 {
-  int rc = check_sim(s);
-  if (rc) return rc;
-  if (n_obs < 0 || (n_obs > 0 && !obs_times)) return fail(KA_EINVAL, "bad observation list");
-  int64_t prev = s->t;
-  for (int q = 0; q < n_obs; ++q) {
-    if (obs_times[q] < prev) return fail(KA_EINVAL, "observation times must be non-decreasing and >= t");
-    prev = obs_times[q];
-  }
-  if (prev >= (1ll << 32)) return fail(KA_ESTATE, "sweep index would reach 2^32");
-  if (n_obs == 0) return KA_OK;
-  DeviceGuard dg(s->device);
-  hipError_t e = ensure_obs_buffers(s, (size_t)n_obs);
-  if (e != hipSuccess) return fail(KA_ENOMEM, "observation buffers: %s", hipGetErrorString(e));
-  const size_t cbytes = (size_t)n_obs * 3u * (size_t)s->R * sizeof(unsigned long long);
-  e = hipMemsetAsync(s->counts, 0, cbytes, s->stream);
-  if (e == hipSuccess && use_lds(s)) {
-    e = hipMemcpyAsync(s->obs_d, obs_times, (size_t)n_obs * sizeof(int64_t), hipMemcpyHostToDevice, s->stream);
-    // chunks [a, b) of at most kLdsChunk sweeps; observation q goes to the first chunk
-    // that can record it (times in [a, b] for the first chunk, (a, b] afterwards)
-    int q = 0;
-    int64_t a = s->t;
-    bool first = true;
-    while (e == hipSuccess && q < n_obs) {
-      const int64_t b = std::min(a + kLdsChunk, obs_times[n_obs - 1]);
-      int q1 = q;
-      while (q1 < n_obs && obs_times[q1] <= b && (first || obs_times[q1] > a)) ++q1;
-      e = launch_lds(s, a, b, q, q1);
-      q = q1;
-      a = b;
-      first = false;
+  return ka_guard([&]() -> int {
+    int rc = check_sim(s);
+    if (rc) return rc;
+    if (n_obs < 0 || (n_obs > 0 && !obs_times)) return fail(KA_EINVAL, "bad observation list");
+    int64_t prev = s->t;
+    for (int q = 0; q < n_obs; ++q) {
+      if (obs_times[q] < prev) return fail(KA_EINVAL, "observation times must be non-decreasing and >= t");
+      prev = obs_times[q];
     }
-  } else {
-    for (int q = 0; q < n_obs && e == hipSuccess; ++q) {
-      const int64_t n = obs_times[q] - s->t;
-      e = sweep_global(s, n);
-      s->t = obs_times[q];
-      if (e == hipSuccess) e = observe_global(s, q);
+    if (prev >= (1ll << 32)) return fail(KA_ESTATE, "sweep index would reach 2^32");
+    if (n_obs == 0) return KA_OK;
+    DeviceGuard dg(s->device);
+    hipError_t e = ensure_obs_buffers(s, (size_t)n_obs);
+    if (e != hipSuccess) return fail(KA_ENOMEM, "observation buffers: %s", hipGetErrorString(e));
+    const size_t cbytes = (size_t)n_obs * 3u * (size_t)s->R * sizeof(unsigned long long);
+    e = hipMemsetAsync(s->counts, 0, cbytes, s->stream);
+    if (e == hipSuccess && use_lds(s)) {
+      e = hipMemcpyAsync(s->obs_d, obs_times, (size_t)n_obs * sizeof(int64_t), hipMemcpyHostToDevice, s->stream);
+      // chunks [a, b) of at most kLdsChunk sweeps; observation q goes to the first chunk
+      // that can record it (times in [a, b] for the first chunk, (a, b] afterwards)
+      int q = 0;
+      int64_t a = s->t;
+      bool first = true;
+      while (e == hipSuccess && q < n_obs) {
+        const int64_t b = std::min(a + kLdsChunk, obs_times[n_obs - 1]);
+        int q1 = q;
+        while (q1 < n_obs && obs_times[q1] <= b && (first || obs_times[q1] > a)) ++q1;
+        e = launch_lds(s, a, b, q, q1);
+        q = q1;
+        a = b;
+        first = false;
+      }
+    } else {
+      for (int q = 0; q < n_obs && e == hipSuccess; ++q) {
+        const int64_t n = obs_times[q] - s->t;
+        e = sweep_global(s, n);
+        s->t = obs_times[q];
+        if (e == hipSuccess) e = observe_global(s, q);
+      }
     }
-  }
-  s->t = obs_times[n_obs - 1];
-  std::vector<unsigned long long> host((size_t)n_obs * 3u * (size_t)s->R);
-  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), s->counts, cbytes, hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(e, "ka_run");
-  rc = check_init_flag(s);
-  if (rc) return rc;
-  harvest_timing(s);
-  for (int q = 0; q < n_obs; ++q)
-    for (int b = 0; b < s->R; ++b) {
-      const size_t base = (size_t)q * 3u * s->R;
-      if (density) density[(size_t)q * s->R + b] = (int64_t)host[base + b];
-      if (overlap) overlap[(size_t)q * s->R + b] = (int64_t)host[base + s->R + b];
-      if (persistence) persistence[(size_t)q * s->R + b] = (int64_t)host[base + 2u * s->R + b];
-    }
-  return KA_OK;
+    s->t = obs_times[n_obs - 1];
+    std::vector<unsigned long long> host((size_t)n_obs * 3u * (size_t)s->R);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), s->counts, cbytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "ka_run");
+    rc = check_init_flag(s);
+    if (rc) return rc;
+    harvest_timing(s);
+    for (int q = 0; q < n_obs; ++q)
+      for (int b = 0; b < s->R; ++b) {
+        const size_t base = (size_t)q * 3u * s->R;
+        if (density) density[(size_t)q * s->R + b] = (int64_t)host[base + b];
+        if (overlap) overlap[(size_t)q * s->R + b] = (int64_t)host[base + s->R + b];
+        if (persistence) persistence[(size_t)q * s->R + b] = (int64_t)host[base + 2u * s->R + b];
+      }
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
                           int64_t *persistence)
 {
-  int rc = check_sim(s);
-  if (rc) return rc;
-  const int64_t now = s->t;
-  rc = ka_run(s, &now, 1, density, overlap, persistence);
-  if (rc) return rc;
-  if (t) *t = s->t;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    int rc = check_sim(s);
+    if (rc) return rc;
+    const int64_t now = s->t;
+    rc = ka_run(s, &now, 1, density, overlap, persistence);
+    if (rc) return rc;
+    if (t) *t = s->t;
+    return KA_OK;
+  });
 }
 
 // Enqueue the counts of ka_observe at the current t on the sim's stream, copied into
@@ -1153,186 +1177,203 @@ int ka_sim_take_own_stream(ka_sim *s, bool wait)
 
 extern "C" int ka_observe_pairs(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *count)
 {
-  int rc = check_sim(s);
-  if (rc) return rc;
-  if (!s->lattice) return fail(KA_EINVAL, "spatial pair sums need a lattice");
-  if (r2_max < 0 || r2_max > ka::kMaxPairShells - 1)
-    return fail(KA_EINVAL, "r2_max must be in [0, %d]", ka::kMaxPairShells - 1);
-  if (s->W > 16) return fail(KA_EINVAL, "spatial pair sums support up to 1024 replicas");
-  const int d = s->geom.d, L = s->geom.L;
-  // every displacement of the torus once, components in the minimum image (|c| <= L/2)
-  std::vector<int4> disp;
-  std::vector<int64_t> cnt((size_t)r2_max + 1, 0);
-  const int n_total = d == 2 ? L * L : L * L * L;
-  for (int q = 0; q < n_total; ++q) {
-    int c[3] = {q % L, (q / L) % L, d == 3 ? q / (L * L) : 0};
-    int r2 = 0;
-    for (int k = 0; k < d; ++k) {
-      if (c[k] > L / 2) c[k] -= L;
-      r2 += c[k] * c[k];
+  return ka_guard([&]() -> int {
+    int rc = check_sim(s);
+    if (rc) return rc;
+    if (!s->lattice) return fail(KA_EINVAL, "spatial pair sums need a lattice");
+    if (r2_max < 0 || r2_max > ka::kMaxPairShells - 1)
+      return fail(KA_EINVAL, "r2_max must be in [0, %d]", ka::kMaxPairShells - 1);
+    if (s->W > 16) return fail(KA_EINVAL, "spatial pair sums support up to 1024 replicas");
+    const int d = s->geom.d, L = s->geom.L;
+    // every displacement of the torus once, components in the minimum image (|c| <= L/2)
+    std::vector<int4> disp;
+    std::vector<int64_t> cnt((size_t)r2_max + 1, 0);
+    const int n_total = d == 2 ? L * L : L * L * L;
+    for (int q = 0; q < n_total; ++q) {
+      int c[3] = {q % L, (q / L) % L, d == 3 ? q / (L * L) : 0};
+      int r2 = 0;
+      for (int k = 0; k < d; ++k) {
+        if (c[k] > L / 2) c[k] -= L;
+        r2 += c[k] * c[k];
+      }
+      if (r2 > r2_max) continue;
+      disp.push_back(make_int4(c[0], c[1], c[2], r2));
+      cnt[(size_t)r2] += 1;
     }
-    if (r2 > r2_max) continue;
-    disp.push_back(make_int4(c[0], c[1], c[2], r2));
-    cnt[(size_t)r2] += 1;
-  }
-  DeviceGuard dg(s->device);
-  int4 *d_disp = nullptr;
-  unsigned long long *d_out = nullptr;
-  const size_t shells = (size_t)r2_max + 1;
-  hipError_t e = dalloc(&d_disp, disp.size() * sizeof(int4));
-  if (e == hipSuccess) e = dalloc(&d_out, 2 * shells * sizeof(unsigned long long));
-  if (e == hipSuccess) e = hipMemcpyAsync(d_disp, disp.data(), disp.size() * sizeof(int4), hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(d_out, 0, 2 * shells * sizeof(unsigned long long), s->stream);
-  if (e == hipSuccess) {
-    ka::PairArgs a{};
-    a.n = s->n;
-    a.n0 = s->n0;
-    a.g = s->geom;
-    a.planes = s->planes;
-    a.disp = d_disp;
-    a.n_disp = (int)disp.size();
-    a.r2_max = r2_max;
-    a.S2 = d_out;
-    a.S11 = d_out + shells;
-    e = ka::launch_pairs(a, s->wpt, s->stream);
-  }
-  std::vector<unsigned long long> host(2 * shells);
-  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), d_out, 2 * shells * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-  (void)hipFree(d_disp);
-  (void)hipFree(d_out);
-  if (e != hipSuccess) return hip_fail(e, "ka_observe_pairs");
-  for (size_t q = 0; q < shells; ++q) {
-    if (S2) S2[q] = (int64_t)host[q];
-    if (S11) S11[q] = (int64_t)host[shells + q];
-    if (count) count[q] = cnt[q];
-  }
-  return KA_OK;
+    DeviceGuard dg(s->device);
+    int4 *d_disp = nullptr;
+    unsigned long long *d_out = nullptr;
+    const size_t shells = (size_t)r2_max + 1;
+    hipError_t e = dalloc(&d_disp, disp.size() * sizeof(int4));
+    if (e == hipSuccess) e = dalloc(&d_out, 2 * shells * sizeof(unsigned long long));
+    if (e == hipSuccess) e = hipMemcpyAsync(d_disp, disp.data(), disp.size() * sizeof(int4), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d_out, 0, 2 * shells * sizeof(unsigned long long), s->stream);
+    if (e == hipSuccess) {
+      ka::PairArgs a{};
+      a.n = s->n;
+      a.n0 = s->n0;
+      a.g = s->geom;
+      a.planes = s->planes;
+      a.disp = d_disp;
+      a.n_disp = (int)disp.size();
+      a.r2_max = r2_max;
+      a.S2 = d_out;
+      a.S11 = d_out + shells;
+      e = ka::launch_pairs(a, s->wpt, s->stream);
+    }
+    std::vector<unsigned long long> host(2 * shells);
+    if (e == hipSuccess) e = hipMemcpyAsync(host.data(), d_out, 2 * shells * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    (void)hipFree(d_disp);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) return hip_fail(e, "ka_observe_pairs");
+    for (size_t q = 0; q < shells; ++q) {
+      if (S2) S2[q] = (int64_t)host[q];
+      if (S11) S11[q] = (int64_t)host[shells + q];
+      if (count) count[q] = cnt[q];
+    }
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, int64_t *t)
 {
-  int rc = check_sim(s);
-  if (rc) return rc;
-  DeviceGuard dg(s->device);
-  const size_t words = (size_t)s->N * s->W;
-  std::vector<u64> buf(words);
-  uint64_t *outs[3] = {n, n0, f};
-  u64 *srcs[3] = {s->n, s->n0, s->f};
-  hipError_t e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(e, "ka_get_state");
-  rc = check_init_flag(s);
-  if (rc) return rc;
-  for (int k = 0; k < 3; ++k) {
-    if (!outs[k]) continue;
-    e = hipMemcpy(buf.data(), srcs[k], words * 8, hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "ka_get_state copy");
-    for (int64_t i = 0; i < s->N; ++i) {
-      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->plan->label[(size_t)i];
-      for (int p = 0; p < s->planes; ++p)
-        for (int w = 0; w < s->wpt; ++w)
-          outs[k][(size_t)(p * s->wpt + w) * s->N + i] = buf[((size_t)p * s->N + el) * s->wpt + w];
+  return ka_guard([&]() -> int {
+    int rc = check_sim(s);
+    if (rc) return rc;
+    DeviceGuard dg(s->device);
+    const size_t words = (size_t)s->N * s->W;
+    std::vector<u64> buf(words);
+    uint64_t *outs[3] = {n, n0, f};
+    u64 *srcs[3] = {s->n, s->n0, s->f};
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "ka_get_state");
+    rc = check_init_flag(s);
+    if (rc) return rc;
+    for (int k = 0; k < 3; ++k) {
+      if (!outs[k]) continue;
+      e = hipMemcpy(buf.data(), srcs[k], words * 8, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(e, "ka_get_state copy");
+      for (int64_t i = 0; i < s->N; ++i) {
+        const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->plan->label[(size_t)i];
+        for (int p = 0; p < s->planes; ++p)
+          for (int w = 0; w < s->wpt; ++w)
+            outs[k][(size_t)(p * s->wpt + w) * s->N + i] = buf[((size_t)p * s->N + el) * s->wpt + w];
+      }
     }
-  }
-  if (t) *t = s->t;
-  return KA_OK;
+    if (t) *t = s->t;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, const uint64_t *f,
                             int64_t t)
 {
-  int rc = check_sim(s);
-  if (rc) return rc;
-  if (!n || !n0 || !f) return fail(KA_EINVAL, "ka_set_state needs n, n0 and f");
-  if (t < 0 || t >= (1ll << 32)) return fail(KA_EINVAL, "t out of range");
-  DeviceGuard dg(s->device);
-  const size_t words = (size_t)s->N * s->W;
-  std::vector<u64> buf(words);
-  const uint64_t *ins[3] = {n, n0, f};
-  u64 *dsts[3] = {s->n, s->n0, s->f};
-  hipError_t e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(e, "ka_set_state");
-  for (int k = 0; k < 3; ++k) {
-    for (int64_t i = 0; i < s->N; ++i) {
-      const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->plan->label[(size_t)i];
-      for (int p = 0; p < s->planes; ++p)
-        for (int w = 0; w < s->wpt; ++w)
-          buf[((size_t)p * s->N + el) * s->wpt + w] = ins[k][(size_t)(p * s->wpt + w) * s->N + i];
+  return ka_guard([&]() -> int {
+    int rc = check_sim(s);
+    if (rc) return rc;
+    if (!n || !n0 || !f) return fail(KA_EINVAL, "ka_set_state needs n, n0 and f");
+    if (t < 0 || t >= (1ll << 32)) return fail(KA_EINVAL, "t out of range");
+    DeviceGuard dg(s->device);
+    const size_t words = (size_t)s->N * s->W;
+    std::vector<u64> buf(words);
+    const uint64_t *ins[3] = {n, n0, f};
+    u64 *dsts[3] = {s->n, s->n0, s->f};
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "ka_set_state");
+    for (int k = 0; k < 3; ++k) {
+      for (int64_t i = 0; i < s->N; ++i) {
+        const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->plan->label[(size_t)i];
+        for (int p = 0; p < s->planes; ++p)
+          for (int w = 0; w < s->wpt; ++w)
+            buf[((size_t)p * s->N + el) * s->wpt + w] = ins[k][(size_t)(p * s->wpt + w) * s->N + i];
+      }
+      e = hipMemcpy(dsts[k], buf.data(), words * 8, hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(e, "ka_set_state copy");
     }
-    e = hipMemcpy(dsts[k], buf.data(), words * 8, hipMemcpyHostToDevice);
-    if (e != hipSuccess) return hip_fail(e, "ka_set_state copy");
-  }
-  s->t = t;
-  return KA_OK;
+    s->t = t;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t *K, int *m,
                            int64_t *t, int *n_classes)
 {
-  if (!s) return fail(KA_EINVAL, "sim is NULL");
-  if (N) *N = s->N;
-  if (n_replicas) *n_replicas = s->R;
-  if (K) *K = s->K;
-  if (m) *m = s->m;
-  if (t) *t = s->t;
-  if (n_classes) *n_classes = s->C;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!s) return fail(KA_EINVAL, "sim is NULL");
+    if (N) *N = s->N;
+    if (n_replicas) *n_replicas = s->R;
+    if (K) *K = s->K;
+    if (m) *m = s->m;
+    if (t) *t = s->t;
+    if (n_classes) *n_classes = s->C;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_set_option(ka_sim *s, int option, int64_t value)
 {
-  if (!s) return fail(KA_EINVAL, "sim is NULL");
-  if (s->batch) return fail(KA_ESTATE, "sim is a batch member");
-  if (option == KA_OPT_PATH) {
-    if (value < 0 || value > 2) return fail(KA_EINVAL, "path must be 0, 1 or 2");
-    if (value == 2 && !s->lds_fits) return fail(KA_EINVAL, "instance does not fit in LDS");
-    s->path_opt = (int)value;
-    return KA_OK;
-  }
-  if (option == KA_OPT_TIMING) {
-    if (value < 0) return fail(KA_EINVAL, "timing interval must be >= 0");
-    s->timing_every = value;
-    return KA_OK;
-  }
-  if (option == KA_OPT_NOISE) {
-    if (value != 0 && value != 1) return fail(KA_EINVAL, "noise must be 0 or 1");
-    s->noise = (int)value;
-    return KA_OK;
-  }
-  return fail(KA_EINVAL, "unknown option %d", option);
+  return ka_guard([&]() -> int {
+    if (!s) return fail(KA_EINVAL, "sim is NULL");
+    if (s->batch) return fail(KA_ESTATE, "sim is a batch member");
+    if (option == KA_OPT_PATH) {
+      if (value < 0 || value > 2) return fail(KA_EINVAL, "path must be 0, 1 or 2");
+      if (value == 2 && !s->lds_fits) return fail(KA_EINVAL, "instance does not fit in LDS");
+      s->path_opt = (int)value;
+      return KA_OK;
+    }
+    if (option == KA_OPT_TIMING) {
+      if (value < 0) return fail(KA_EINVAL, "timing interval must be >= 0");
+      s->timing_every = value;
+      return KA_OK;
+    }
+    if (option == KA_OPT_NOISE) {
+      if (value != 0 && value != 1) return fail(KA_EINVAL, "noise must be 0 or 1");
+      s->noise = (int)value;
+      return KA_OK;
+    }
+    return fail(KA_EINVAL, "unknown option %d", option);
+  });
 }
 
 extern "C" int ka_timing(ka_sim *s, int64_t *launches, int64_t *timed, double *timed_ms)
 {
-  if (!s) return fail(KA_EINVAL, "sim is NULL");
-  DeviceGuard dg(s->device);
-  hipError_t e = hipStreamSynchronize(s->stream);
-  if (e != hipSuccess) return hip_fail(e, "ka_timing");
-  harvest_timing(s);
-  if (launches) *launches = s->launches;
-  if (timed) *timed = s->timed;
-  if (timed_ms) *timed_ms = s->timed_ms;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!s) return fail(KA_EINVAL, "sim is NULL");
+    DeviceGuard dg(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "ka_timing");
+    harvest_timing(s);
+    if (launches) *launches = s->launches;
+    if (timed) *timed = s->timed;
+    if (timed_ms) *timed_ms = s->timed_ms;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_sim_path(const ka_sim *s, int *path)
 {
-  if (!s || !path) return fail(KA_EINVAL, "NULL argument");
-  *path = use_lds(s) ? 2 : 1;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!s || !path) return fail(KA_EINVAL, "NULL argument");
+    *path = use_lds(s) ? 2 : 1;
+    return KA_OK;
+  });
 }
 
 extern "C" void ka_free(ka_sim *s)
 {
-  if (!s) return;
-  if (s->batch) (void)ka_batch_release_member(s->batch, s);
-  DeviceGuard dg(s->device);
-  if (s->stream) (void)hipStreamSynchronize(s->stream);
-  harvest_timing(s);
-  for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
-  free_device(s);
-  if (s->own_stream) (void)hipStreamDestroy(s->stream);
-  delete s;
+  try {
+    if (!s) return;
+    if (s->batch) (void)ka_batch_release_member(s->batch, s);
+    DeviceGuard dg(s->device);
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    harvest_timing(s);
+    for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
+    free_device(s);
+    if (s->own_stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+  } catch (...) {
+  }
 }
 
 extern "C" const char *ka_last_error(void) { return g_err.c_str(); }

@@ -4,8 +4,10 @@
 
 #include <stdint.h>
 
+#include <exception>
 #include <memory>
 #include <mutex>
+#include <new>
 #include <utility>
 #include <vector>
 
@@ -92,3 +94,22 @@ int ka_sim_take_own_stream(ka_sim *s, bool wait);
 // Bind the sim to `stream`, which the caller has already ordered after the sim's pending work.
 void ka_sim_rebind_stream(ka_sim *s, hipStream_t stream);
 
+// Runs the body of a C entry point: an exception thrown inside (a failed host allocation, or
+// anything else from the standard library) becomes an error code and a message instead of
+// crossing the C boundary.
+template <typename F>
+int ka_guard(F &&body) noexcept
+{
+  try {
+    return body();
+  } catch (const std::bad_alloc &) {
+    ka_set_error("host allocation failed");
+    return KA_ENOMEM;
+  } catch (const std::exception &e) {
+    ka_set_error(e.what());
+    return KA_EDEVICE;
+  } catch (...) {
+    ka_set_error("unexpected exception");
+    return KA_EDEVICE;
+  }
+}

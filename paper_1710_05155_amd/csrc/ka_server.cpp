@@ -312,209 +312,228 @@ void worker_main(ka_server *sv)
 
 extern "C" int ka_server_create(size_t device_budget, int max_active, void *hip_stream, ka_server **out)
 {
-  if (!out) return sfail(KA_EINVAL, "out is NULL");
-  *out = nullptr;
-  if (max_active < 1 || max_active > ka::kBatchMaxMembers)
-    return sfail(KA_EINVAL, "max_active must be in [1, %d]", ka::kBatchMaxMembers);
-  if (device_budget == 0) return sfail(KA_EINVAL, "device budget is 0");
-  ka_server *sv = new (std::nothrow) ka_server;
-  if (!sv) return sfail(KA_ENOMEM, "host allocation failed");
-  sv->budget = device_budget;
-  sv->max_active = max_active;
-  (void)hipGetDevice(&sv->device);
-  hipError_t e = hipSuccess;
-  if (hip_stream) {
-    sv->stream = (hipStream_t)hip_stream;
-  } else {
-    e = hipStreamCreate(&sv->stream);
-    sv->own_stream = e == hipSuccess;
-  }
-  if (e != hipSuccess) {
-    delete sv;
-    return sfail(KA_EDEVICE, "stream: %s", hipGetErrorString(e));
-  }
-  e = hipStreamCreate(&sv->init_stream);
-  if (e != hipSuccess) {
-    if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
-    delete sv;
-    return sfail(KA_EDEVICE, "stream: %s", hipGetErrorString(e));
-  }
-  int rc = ka_batch_create(max_active, sv->stream, &sv->batch);
-  if (rc != KA_OK) {
-    (void)hipStreamDestroy(sv->init_stream);
-    if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
-    delete sv;
-    return rc;
-  }
-  // members come and go, so tuning on the first job's steps would not be representative
-  (void)ka_batch_set_option(sv->batch, KA_BOPT_AUTOTUNE, 0);
-  sv->worker = std::thread(worker_main, sv);
-  *out = sv;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!out) return sfail(KA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_active < 1 || max_active > ka::kBatchMaxMembers)
+      return sfail(KA_EINVAL, "max_active must be in [1, %d]", ka::kBatchMaxMembers);
+    if (device_budget == 0) return sfail(KA_EINVAL, "device budget is 0");
+    ka_server *sv = new (std::nothrow) ka_server;
+    if (!sv) return sfail(KA_ENOMEM, "host allocation failed");
+    sv->budget = device_budget;
+    sv->max_active = max_active;
+    (void)hipGetDevice(&sv->device);
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+      sv->stream = (hipStream_t)hip_stream;
+    } else {
+      e = hipStreamCreate(&sv->stream);
+      sv->own_stream = e == hipSuccess;
+    }
+    if (e != hipSuccess) {
+      delete sv;
+      return sfail(KA_EDEVICE, "stream: %s", hipGetErrorString(e));
+    }
+    e = hipStreamCreate(&sv->init_stream);
+    if (e != hipSuccess) {
+      if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
+      delete sv;
+      return sfail(KA_EDEVICE, "stream: %s", hipGetErrorString(e));
+    }
+    int rc = ka_batch_create(max_active, sv->stream, &sv->batch);
+    if (rc != KA_OK) {
+      (void)hipStreamDestroy(sv->init_stream);
+      if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
+      delete sv;
+      return rc;
+    }
+    // members come and go, so tuning on the first job's steps would not be representative
+    (void)ka_batch_set_option(sv->batch, KA_BOPT_AUTOTUNE, 0);
+    sv->worker = std::thread(worker_main, sv);
+    *out = sv;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_server_submit(ka_server *sv, const ka_job_desc *job, int64_t *job_id)
 {
-  if (!sv || !job || !job->graph) return sfail(KA_EINVAL, "NULL argument");
-  if (job->n_sweeps < 0 || job->n_sweeps >= (1ll << 32)) return sfail(KA_EINVAL, "n_sweeps out of range");
-  if (job->n_replicas <= 0 || job->n_replicas % 64 != 0) return sfail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
-  int64_t N = 0;
-  int z = 0;
-  ka_graph_info(job->graph, &N, &z, nullptr, nullptr);
-  if (job->m < 0 || job->m > z - 1) return sfail(KA_EINVAL, "m out of range");
-  if (!(job->rho >= 0.0 && job->rho <= 1.0)) return sfail(KA_EINVAL, "rho out of range");
-  auto j = std::make_unique<Job>();
-  j->graph = job->graph;
-  j->m = job->m;
-  j->rho = job->rho;
-  j->seed = job->seed;
-  j->R = job->n_replicas;
-  j->sweeps = job->n_sweeps;
-  j->keep = job->keep_sim != 0;
-  if (job->obs_times && job->n_obs > 0) {
-    int64_t prev = 0;
-    for (int q = 0; q < job->n_obs; ++q) {
-      const int64_t v = job->obs_times[q];
-      if (v < prev || v > job->n_sweeps) return sfail(KA_EINVAL, "observation times must be non-decreasing in [0, n_sweeps]");
-      j->obs.push_back(v);
-      prev = v;
+  return ka_guard([&]() -> int {
+    if (!sv || !job || !job->graph) return sfail(KA_EINVAL, "NULL argument");
+    if (job->n_sweeps < 0 || job->n_sweeps >= (1ll << 32)) return sfail(KA_EINVAL, "n_sweeps out of range");
+    if (job->n_replicas <= 0 || job->n_replicas % 64 != 0) return sfail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
+    int64_t N = 0;
+    int z = 0;
+    ka_graph_info(job->graph, &N, &z, nullptr, nullptr);
+    if (job->m < 0 || job->m > z - 1) return sfail(KA_EINVAL, "m out of range");
+    if (!(job->rho >= 0.0 && job->rho <= 1.0)) return sfail(KA_EINVAL, "rho out of range");
+    auto j = std::make_unique<Job>();
+    j->graph = job->graph;
+    j->m = job->m;
+    j->rho = job->rho;
+    j->seed = job->seed;
+    j->R = job->n_replicas;
+    j->sweeps = job->n_sweeps;
+    j->keep = job->keep_sim != 0;
+    if (job->obs_times && job->n_obs > 0) {
+      int64_t prev = 0;
+      for (int q = 0; q < job->n_obs; ++q) {
+        const int64_t v = job->obs_times[q];
+        if (v < prev || v > job->n_sweeps) return sfail(KA_EINVAL, "observation times must be non-decreasing in [0, n_sweeps]");
+        j->obs.push_back(v);
+        prev = v;
+      }
+    } else {
+      j->obs.push_back(job->n_sweeps);
     }
-  } else {
-    j->obs.push_back(job->n_sweeps);
-  }
-  if (ka_footprint(job->graph, job->n_replicas, &j->footprint) != KA_OK) return KA_EINVAL;
-  j->footprint += j->obs.size() * 3u * (size_t)job->n_replicas * 8u;
-  if (j->footprint > sv->budget) return sfail(KA_EINVAL, "job needs %zu device bytes, budget is %zu", j->footprint, sv->budget);
-  j->attempts = (double)N * (double)job->n_replicas * (double)job->n_sweeps;
-  j->t_submit = Clock::now();
-  std::lock_guard<std::mutex> lk(sv->mu);
-  j->id = sv->next_id++;
-  if (job_id) *job_id = j->id;
-  sv->incoming.push_back(std::move(j));
-  sv->submitted += 1;
-  sv->cv_work.notify_one();
-  return KA_OK;
+    if (ka_footprint(job->graph, job->n_replicas, &j->footprint) != KA_OK) return KA_EINVAL;
+    j->footprint += j->obs.size() * 3u * (size_t)job->n_replicas * 8u;
+    if (j->footprint > sv->budget) return sfail(KA_EINVAL, "job needs %zu device bytes, budget is %zu", j->footprint, sv->budget);
+    j->attempts = (double)N * (double)job->n_replicas * (double)job->n_sweeps;
+    j->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    j->id = sv->next_id++;
+    if (job_id) *job_id = j->id;
+    sv->incoming.push_back(std::move(j));
+    sv->submitted += 1;
+    sv->cv_work.notify_one();
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_server_poll(ka_server *sv, int64_t *job_ids, int max_ids, int *n)
 {
-  if (!sv) return sfail(KA_EINVAL, "server is NULL");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  int got = 0;
-  while (got < max_ids && !sv->done_ids.empty()) {
-    if (job_ids) job_ids[got] = sv->done_ids.front();
-    sv->done_ids.erase(sv->done_ids.begin());
-    ++got;
-  }
-  if (n) *n = got;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!sv) return sfail(KA_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    int got = 0;
+    while (got < max_ids && !sv->done_ids.empty()) {
+      if (job_ids) job_ids[got] = sv->done_ids.front();
+      sv->done_ids.erase(sv->done_ids.begin());
+      ++got;
+    }
+    if (n) *n = got;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_server_result(ka_server *sv, int64_t job_id, int64_t *density, int64_t *overlap,
                                 int64_t *persistence, double *wait_s, double *latency_s)
 {
-  if (!sv) return sfail(KA_EINVAL, "server is NULL");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  auto it = sv->finished.find(job_id);
-  if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
-  Job *j = it->second.get();
-  if (j->rc != KA_OK) return sfail(j->rc, "job %lld failed", (long long)job_id);
-  if (j->counts.size() != j->obs.size() * 3u * (size_t)j->R)
-    return sfail(KA_ESTATE, "job %lld has no counts", (long long)job_id);
-  const size_t R = (size_t)j->R;
-  for (size_t q = 0; q < j->obs.size(); ++q)
-    for (size_t b = 0; b < R; ++b) {
-      const int64_t *row = j->counts.data() + q * 3u * R;
-      if (density) density[q * R + b] = row[b];
-      if (overlap) overlap[q * R + b] = row[R + b];
-      if (persistence) persistence[q * R + b] = row[2 * R + b];
-    }
-  if (wait_s) *wait_s = std::chrono::duration<double>(j->t_admit - j->t_submit).count();
-  if (latency_s) *latency_s = std::chrono::duration<double>(j->t_done - j->t_submit).count();
-  return KA_OK;
-}
-
-extern "C" int ka_server_take_sim(ka_server *sv, int64_t job_id, ka_sim **out)
-{
-  if (!sv || !out) return sfail(KA_EINVAL, "NULL argument");
-  ka_sim *sim = nullptr;
-  {
+  return ka_guard([&]() -> int {
+    if (!sv) return sfail(KA_EINVAL, "server is NULL");
     std::lock_guard<std::mutex> lk(sv->mu);
     auto it = sv->finished.find(job_id);
     if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
     Job *j = it->second.get();
-    if (!j->keep || !j->sim) return sfail(KA_ESTATE, "job %lld kept no sim", (long long)job_id);
-    sim = j->sim;
-    j->sim = nullptr;
-  }
-  // The server's own stream ends with the server, so the sim gets a stream of its own.  The
-  // job is complete (its last copy has landed), so nothing of the sim is pending.
-  if (sv->own_stream) {
-    const int rc = ka_sim_take_own_stream(sim, false);
-    if (rc != KA_OK) {
-      ka_free(sim);
-      return rc;
+    if (j->rc != KA_OK) return sfail(j->rc, "job %lld failed", (long long)job_id);
+    if (j->counts.size() != j->obs.size() * 3u * (size_t)j->R)
+      return sfail(KA_ESTATE, "job %lld has no counts", (long long)job_id);
+    const size_t R = (size_t)j->R;
+    for (size_t q = 0; q < j->obs.size(); ++q)
+      for (size_t b = 0; b < R; ++b) {
+        const int64_t *row = j->counts.data() + q * 3u * R;
+        if (density) density[q * R + b] = row[b];
+        if (overlap) overlap[q * R + b] = row[R + b];
+        if (persistence) persistence[q * R + b] = row[2 * R + b];
+      }
+    if (wait_s) *wait_s = std::chrono::duration<double>(j->t_admit - j->t_submit).count();
+    if (latency_s) *latency_s = std::chrono::duration<double>(j->t_done - j->t_submit).count();
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_server_take_sim(ka_server *sv, int64_t job_id, ka_sim **out)
+{
+  return ka_guard([&]() -> int {
+    if (!sv || !out) return sfail(KA_EINVAL, "NULL argument");
+    ka_sim *sim = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      auto it = sv->finished.find(job_id);
+      if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
+      Job *j = it->second.get();
+      if (!j->keep || !j->sim) return sfail(KA_ESTATE, "job %lld kept no sim", (long long)job_id);
+      sim = j->sim;
+      j->sim = nullptr;
     }
-  }
-  *out = sim;
-  return KA_OK;
+    // The server's own stream ends with the server, so the sim gets a stream of its own.  The
+    // job is complete (its last copy has landed), so nothing of the sim is pending.
+    if (sv->own_stream) {
+      const int rc = ka_sim_take_own_stream(sim, false);
+      if (rc != KA_OK) {
+        ka_free(sim);
+        return rc;
+      }
+    }
+    *out = sim;
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_server_release(ka_server *sv, int64_t job_id)
 {
-  if (!sv) return sfail(KA_EINVAL, "server is NULL");
-  std::unique_ptr<Job> jp;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    auto it = sv->finished.find(job_id);
-    if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
-    jp = std::move(it->second);
-    sv->finished.erase(it);
-    sv->done_ids.erase(std::remove(sv->done_ids.begin(), sv->done_ids.end(), job_id), sv->done_ids.end());
-  }
-  if (jp->sim) ka_free(jp->sim);   // the job is complete: nothing of it runs on the device
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!sv) return sfail(KA_EINVAL, "server is NULL");
+    std::unique_ptr<Job> jp;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      auto it = sv->finished.find(job_id);
+      if (it == sv->finished.end()) return sfail(KA_ESTATE, "job %lld is not complete", (long long)job_id);
+      jp = std::move(it->second);
+      sv->finished.erase(it);
+      sv->done_ids.erase(std::remove(sv->done_ids.begin(), sv->done_ids.end(), job_id), sv->done_ids.end());
+    }
+    if (jp->sim) ka_free(jp->sim);   // the job is complete: nothing of it runs on the device
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_server_wait_idle(ka_server *sv)
 {
-  if (!sv) return sfail(KA_EINVAL, "server is NULL");
-  std::unique_lock<std::mutex> lk(sv->mu);
-  sv->cv_done.wait(lk, [&] { return sv->completed == sv->submitted; });
-  if (!sv->worker_error.empty()) return sfail(KA_EDEVICE, "worker: %s", sv->worker_error.c_str());
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!sv) return sfail(KA_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(sv->mu);
+    sv->cv_done.wait(lk, [&] { return sv->completed == sv->submitted; });
+    if (!sv->worker_error.empty()) return sfail(KA_EDEVICE, "worker: %s", sv->worker_error.c_str());
+    return KA_OK;
+  });
 }
 
 extern "C" int ka_server_stats(ka_server *sv, int64_t *jobs_done, double *attempts, int *peak_active,
                                size_t *peak_bytes)
 {
-  if (!sv) return sfail(KA_EINVAL, "server is NULL");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  if (jobs_done) *jobs_done = sv->completed;
-  if (attempts) *attempts = sv->attempts_done;
-  if (peak_active) *peak_active = sv->peak_active;
-  if (peak_bytes) *peak_bytes = sv->peak_bytes;
-  return KA_OK;
+  return ka_guard([&]() -> int {
+    if (!sv) return sfail(KA_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (jobs_done) *jobs_done = sv->completed;
+    if (attempts) *attempts = sv->attempts_done;
+    if (peak_active) *peak_active = sv->peak_active;
+    if (peak_bytes) *peak_bytes = sv->peak_bytes;
+    return KA_OK;
+  });
 }
 
 extern "C" void ka_server_free(ka_server *sv)
 {
-  if (!sv) return;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    sv->stop = true;
-    sv->cv_work.notify_all();
+  try {
+    if (!sv) return;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      sv->stop = true;
+      sv->cv_work.notify_all();
+    }
+    if (sv->worker.joinable()) sv->worker.join();
+    ka_batch_free(sv->batch);
+    for (auto &kv : sv->finished) {
+      Job *j = kv.second.get();
+      if (j->sim) ka_free(j->sim);
+      if (j->pinned) (void)hipHostFree(j->pinned);
+      if (j->done_ev) (void)hipEventDestroy(j->done_ev);
+    }
+    (void)hipStreamSynchronize(sv->init_stream);
+    (void)hipStreamDestroy(sv->init_stream);
+    if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
+    delete sv;
+  } catch (...) {
   }
-  if (sv->worker.joinable()) sv->worker.join();
-  ka_batch_free(sv->batch);
-  for (auto &kv : sv->finished) {
-    Job *j = kv.second.get();
-    if (j->sim) ka_free(j->sim);
-    if (j->pinned) (void)hipHostFree(j->pinned);
-    if (j->done_ev) (void)hipEventDestroy(j->done_ev);
-  }
-  (void)hipStreamSynchronize(sv->init_stream);
-  (void)hipStreamDestroy(sv->init_stream);
-  if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
-  delete sv;
 }
