@@ -273,8 +273,8 @@ int ka_server_result(ka_server *sv, int64_t job_id, int64_t *density, int64_t *o
 
 /* Hand over the final sim of a completed job submitted with keep_sim; the caller frees it
  * with ka_free.  A kept sim belongs to the caller once its job completes and no longer counts
- * against the budget.  If the server created its own stream, the sim moves to a stream of its
- * own, so it may outlive the server. */
+ * against the budget.  The sim moves to a stream of its own (created by the library), so it may
+ * outlive the server and never waits on the server's stream. */
 int ka_server_take_sim(ka_server *sv, int64_t job_id, ka_sim **out);
 
 /* Forget a completed job: drop its results and free its kept sim if it was not taken.

@@ -240,6 +240,13 @@ hipError_t enqueue_steps(ka_batch *b, int64_t n)
       int64_t left = chunk;
       while (e == hipSuccess && b->graph_steps > 0 && left >= b->graph_steps) {
         e = launch_graph(b);
+        if (e != hipSuccess) {
+          // Nothing of a failed capture, instantiation or graph launch has run (for instance,
+          // another thread used the legacy stream during the capture): the same steps are
+          // launched directly.
+          (void)hipGetLastError();
+          e = launch_steps(b, b->graph_steps);
+        }
         left -= b->graph_steps;
       }
       while (e == hipSuccess && left > 0) {
@@ -352,7 +359,7 @@ extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
     if (hip_stream) {
       b->stream = (hipStream_t)hip_stream;
     } else {
-      e = hipStreamCreate(&b->stream);
+      e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
       b->own_stream = e == hipSuccess;
     }
     if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_tab, sizeof(ka::BatchMember) * (size_t)capacity, hipHostMallocDefault);

@@ -702,7 +702,8 @@ int check_init_flag(ka_sim *s)
 {
   if (s->init_checked) return KA_OK;
   int flag = 0;
-  hipError_t e = hipMemcpy(&flag, s->err, sizeof(int), hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpyAsync(&flag, s->err, sizeof(int), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
   if (e != hipSuccess) return hip_fail(e, "reading the init status");
   s->init_checked = true;
   if (flag) return fail(KA_EDEVICE, "initial-state selection failed (flag %d)", flag);
@@ -932,7 +933,7 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
     if (hip_stream) {
       s->stream = (hipStream_t)hip_stream;
     } else {
-      hipError_t e = hipStreamCreate(&s->stream);
+      hipError_t e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
       if (e != hipSuccess) {
         delete s;
         return hip_fail(e, "hipStreamCreate");
@@ -1167,7 +1168,7 @@ int ka_sim_take_own_stream(ka_sim *s, bool wait)
   DeviceGuard dg(s->device);
   hipError_t e = wait ? hipStreamSynchronize(s->stream) : hipSuccess;
   hipStream_t fresh = nullptr;
-  if (e == hipSuccess) e = hipStreamCreate(&fresh);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&fresh, hipStreamNonBlocking);
   if (e != hipSuccess) return hip_fail(e, "stream");
   if (s->own_stream) (void)hipStreamDestroy(s->stream);
   s->stream = fresh;
@@ -1252,7 +1253,8 @@ extern "C" int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, i
     if (rc) return rc;
     for (int k = 0; k < 3; ++k) {
       if (!outs[k]) continue;
-      e = hipMemcpy(buf.data(), srcs[k], words * 8, hipMemcpyDeviceToHost);
+      e = hipMemcpyAsync(buf.data(), srcs[k], words * 8, hipMemcpyDeviceToHost, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       if (e != hipSuccess) return hip_fail(e, "ka_get_state copy");
       for (int64_t i = 0; i < s->N; ++i) {
         const int64_t el = s->lattice ? lattice_element(s->geom, i) : s->plan->label[(size_t)i];
@@ -1288,7 +1290,8 @@ extern "C" int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, co
           for (int w = 0; w < s->wpt; ++w)
             buf[((size_t)p * s->N + el) * s->wpt + w] = ins[k][(size_t)(p * s->wpt + w) * s->N + i];
       }
-      e = hipMemcpy(dsts[k], buf.data(), words * 8, hipMemcpyHostToDevice);
+      e = hipMemcpyAsync(dsts[k], buf.data(), words * 8, hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       if (e != hipSuccess) return hip_fail(e, "ka_set_state copy");
     }
     s->t = t;

@@ -277,8 +277,16 @@ void worker_main(ka_server *sv)
       if (left > 0) {
         const int rc = ka_batch_run(sv->batch, std::min(left, kChunkSteps));
         if (rc != KA_OK) {
-          std::lock_guard<std::mutex> lk(sv->mu);
-          sv->worker_error = ka_last_error();
+          {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->worker_error = ka_last_error();
+          }
+          // The batch cannot advance: its jobs end with the error instead of waiting for ever.
+          for (auto &kv : sv->active) {
+            kv.second->rc = rc;
+            finish(sv, std::move(kv.second));
+          }
+          sv->active.clear();
         }
         hipEvent_t ev = nullptr;
         if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess) {
@@ -327,14 +335,14 @@ extern "C" int ka_server_create(size_t device_budget, int max_active, void *hip_
     if (hip_stream) {
       sv->stream = (hipStream_t)hip_stream;
     } else {
-      e = hipStreamCreate(&sv->stream);
+      e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
       sv->own_stream = e == hipSuccess;
     }
     if (e != hipSuccess) {
       delete sv;
       return sfail(KA_EDEVICE, "stream: %s", hipGetErrorString(e));
     }
-    e = hipStreamCreate(&sv->init_stream);
+    e = hipStreamCreateWithFlags(&sv->init_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
       if (sv->own_stream) (void)hipStreamDestroy(sv->stream);
       delete sv;
@@ -456,14 +464,13 @@ extern "C" int ka_server_take_sim(ka_server *sv, int64_t job_id, ka_sim **out)
       sim = j->sim;
       j->sim = nullptr;
     }
-    // The server's own stream ends with the server, so the sim gets a stream of its own.  The
-    // job is complete (its last copy has landed), so nothing of the sim is pending.
-    if (sv->own_stream) {
-      const int rc = ka_sim_take_own_stream(sim, false);
-      if (rc != KA_OK) {
-        ka_free(sim);
-        return rc;
-      }
+    // The sim gets a stream of its own: the server's stream may end with the server, and the
+    // worker may be capturing a graph on it, which the caller's thread must not synchronise.
+    // The job is complete (its last copy has landed), so nothing of the sim is pending.
+    const int rc = ka_sim_take_own_stream(sim, false);
+    if (rc != KA_OK) {
+      ka_free(sim);
+      return rc;
     }
     *out = sim;
     return KA_OK;
@@ -483,7 +490,13 @@ extern "C" int ka_server_release(ka_server *sv, int64_t job_id)
       sv->finished.erase(it);
       sv->done_ids.erase(std::remove(sv->done_ids.begin(), sv->done_ids.end(), job_id), sv->done_ids.end());
     }
-    if (jp->sim) ka_free(jp->sim);   // the job is complete: nothing of it runs on the device
+    // The job is complete, so nothing of its sim is pending.  It moves to a stream of its own
+    // before it is freed: the worker may be capturing a graph on the server's stream, which
+    // another thread must not synchronise.
+    if (jp->sim) {
+      (void)ka_sim_take_own_stream(jp->sim, false);
+      ka_free(jp->sim);
+    }
     return KA_OK;
   });
 }

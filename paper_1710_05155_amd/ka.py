@@ -496,7 +496,7 @@ def ka_server_result(sv: Server, job_id: int):
 def ka_server_take_sim(sv: Server, job_id: int) -> Sim:
     h = ctypes.c_void_p()
     _check(load().ka_server_take_sim(sv.handle, int(job_id), ctypes.byref(h)))
-    return Sim(h, sv.jobs[job_id][0], sv.stream)
+    return Sim(h, sv.jobs[job_id][0], None)   # the sim now has a stream of its own
 
 
 def ka_server_release(sv: Server, job_id: int) -> None:

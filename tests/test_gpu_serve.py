@@ -147,3 +147,36 @@ def test_release_and_taken_sim_outlives_server(graphs):
     assert np.array_equal(ov, o1[0]) and np.array_equal(pers, p1[0]) and np.array_equal(dens, d1[0])
     for x, y in zip(state, solo_state):
         assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_take_and_release_while_others_run(graphs):
+    """Completed jobs are taken (and swept further) or released from the caller's thread while
+    the worker keeps running later jobs; every taken sim equals its solo run."""
+    _say("serve: take / release while running")
+    sv = ka.ka_server_create(1 << 34, 3)
+    ids = {}
+    done, taken = 0, {}
+    try:
+        for k, (key, m, rho, R, seed, sweeps, obs) in enumerate(JOBS):
+            ids[ka.ka_server_submit(sv, graphs[key], m, rho, seed, R, sweeps, obs_times=obs,
+                                    keep_sim=True)] = k
+        deadline = time.time() + 120
+        while done < len(ids):
+            assert time.time() < deadline, "jobs did not complete"
+            for jid in ka.ka_server_poll(sv):
+                k = ids[jid]
+                done += 1
+                if k % 2 == 0:
+                    sim = ka.ka_server_take_sim(sv, jid)
+                    ka.ka_sweep(sim, 2)
+                    taken[k] = ka.ka_get_state(sim)
+                    sim.free()
+                ka.ka_server_release(sv, jid)
+            time.sleep(0.001)
+    finally:
+        sv.free()
+    for k, state in taken.items():
+        key, m, rho, R, seed, sweeps, obs = JOBS[k]
+        _, solo_state = _solo(graphs[key], m, rho, R, seed, sweeps + 2, None)
+        for a, b in zip(state, solo_state):
+            assert np.array_equal(np.asarray(a), np.asarray(b)), k
