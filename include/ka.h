@@ -33,6 +33,9 @@
  *   - A ka_sim is bound to one device (the current one at ka_init) and one HIP stream.  No
  *     two host threads may use the same ka_sim at once.  ka_graph objects are immutable and
  *     may be shared and freed once the sims built from them exist.
+ *   - Streams the library creates are non-blocking (hipStreamNonBlocking), and all device work
+ *     of a call, copies included, runs on the object's stream; the library never uses the
+ *     legacy default stream.
  *   - Canonical state export layout: uint64 [W][N], W = n_replicas / 64; bit (b & 63) of
  *     word [b >> 6][i] is replica b at site i.  The device layout is private.
  *   - The sweep index t counts sweeps since ka_init; it is part of the random counter, so a
