@@ -94,6 +94,9 @@ RRG_CASES = [
     (300, 6, 3, 0.8, 256),
     (300, 6, 0, 0.4, 64),
     (2000, 4, 2, 0.65, 192),
+    # complete graphs K4 and K6: every pair of edges conflicts, so each class is one edge
+    (4, 3, 1, 0.5, 64),
+    (6, 5, 2, 0.5, 128),
 ]
 
 
