@@ -441,17 +441,28 @@ __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int4 *edges, 
 }
 
 // ------------------------------------------------------------------------------------
-// Vertical (per-replica) population counts with wavefront ballots: lane l of the wave
-// accumulates, for replica bit l, the number of the wave's 64 sites whose bit l is set.
+// Vertical (per-replica) population counts: the wave's 64 words (one site per lane) are
+// transposed as a 64 x 64 bit matrix in six butterfly stages (lanes i and i ^ s swap the
+// off-diagonal s x s blocks), after which lane l holds bit l of every lane's word, and its
+// popcount is the number of the wave's sites whose bit l is set; lane l accumulates that
+// into acc.  All 64 lanes must take part (wave-uniform control flow).
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void ballot_count(u64 x, unsigned &acc)
+__device__ __forceinline__ void vertical_count(u64 x, unsigned &acc)
 {
   const int lane = (int)__lane_id();
+  constexpr u64 kMask[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                            0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
 #pragma unroll
-  for (int l = 0; l < 64; ++l) {
-    const unsigned c = (unsigned)__popcll(__ballot((int)((x >> l) & 1ull)));
-    acc += (lane == l) ? c : 0u;
+  for (int k = 0; k < 6; ++k) {
+    const int sh = 32 >> k;
+    const u64 m = kMask[k];
+    const u64 y = __shfl_xor(x, sh);
+    const u64 lo = (x & m) | ((y & m) << sh);     // lanes with bit sh clear
+    const u64 hi = ((y >> sh) & m) | (x & ~m);    // lanes with bit sh set
+    const u64 sel = 0ull - (u64)((lane >> (5 - k)) & 1);   // all ones where bit sh is set
+    x = (lo & ~sel) | (hi & sel);
   }
+  acc += (unsigned)__popcll(x);
 }
 
 }  // namespace dev

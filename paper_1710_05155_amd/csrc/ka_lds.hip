@@ -41,9 +41,9 @@ __device__ void lds_observe(const SweepLds &a, const u64 *sn, const u64 *sf, int
     }
 #pragma unroll
     for (int w = 0; w < WPT; ++w) {
-      ballot_count(x.w[w], acc[0][w]);
-      ballot_count(x.w[w] & x0.w[w], acc[1][w]);
-      ballot_count(x0.w[w] & ~xf.w[w], acc[2][w]);
+      vertical_count(x.w[w], acc[0][w]);
+      vertical_count(x.w[w] & x0.w[w], acc[1][w]);
+      vertical_count(x0.w[w] & ~xf.w[w], acc[2][w]);
     }
   }
 #pragma unroll
