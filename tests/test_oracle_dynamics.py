@@ -48,6 +48,20 @@ def test_init_uniform_k_subsets(oracle):
     assert chi2 < 30.0, chi2  # 5 dof; 30 is p ~ 1.5e-5
 
 
+def test_particle_count_from_density(oracle):
+    """K = floor(rho N + 1/2) in IEEE double: the counts of the measured workloads (2D L=64
+    at rho=0.70; 3D L=128 at 0.80, 0.85, 0.88; RRG N=2^20 at 0.50..0.75), and ties at an
+    exact half round up (never to even)."""
+    assert oracle.k_from_rho(64 ** 2, 0.70) == 2867
+    assert [oracle.k_from_rho(128 ** 3, r) for r in (0.80, 0.85, 0.88)] == [1677722, 1782579, 1845494]
+    assert [oracle.k_from_rho(2 ** 20, r) for r in (0.50, 0.55, 0.60, 0.65, 0.70, 0.75)] == \
+        [524288, 576717, 629146, 681574, 734003, 786432]
+    assert oracle.k_from_rho(2, 0.25) == 1          # rho N = 0.5
+    assert oracle.k_from_rho(8, 0.3125) == 3        # 2.5
+    assert oracle.k_from_rho(16, 0.90625) == 15     # 14.5
+    assert oracle.k_from_rho(10, 0.0) == 0 and oracle.k_from_rho(10, 1.0) == 10
+
+
 def test_init_occupies_smallest_keys(oracle):
     g = oracle.lattice(2, 8)
     seed, K = 123456789, 20
