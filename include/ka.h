@@ -248,7 +248,7 @@ void ka_batch_free(ka_batch *b);
 typedef struct ka_server ka_server;
 
 typedef struct {
-  const ka_graph *graph;     /* borrowed: must stay valid until the job has started     */
+  const ka_graph *graph;     /* borrowed: keep it valid until the job is reported done  */
   int m;                     /* activation number                                       */
   double rho;                /* density; K = floor(rho*N + 1/2)                          */
   uint64_t seed;

@@ -95,11 +95,17 @@ __global__ __launch_bounds__(1024) void k_batch_prepare(const BatchMember *mem, 
   }
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    const int a = start[k], b = start[k + 1];
+    const int a = start[k], b = min(start[k + 1], tiles.cap);
     for (int q = a + tid; q < b; q += (int)blockDim.x) {
       tiles.member[q] = k;
       tiles.local[q] = q - a;
     }
+  }
+  // The host computes the same total from the same table; should they ever differ, tiles
+  // past the total run nothing instead of reading stale entries.
+  for (int q = start[n] + tid; q < tiles.cap; q += (int)blockDim.x) {
+    tiles.member[q] = -1;
+    tiles.local[q] = 0;
   }
 }
 
@@ -110,6 +116,7 @@ __global__ __launch_bounds__(BLOCK) void k_batch_step(const BatchMember *mem, Ba
   const int tile = xcd_remap((int)blockIdx.x, (int)gridDim.x);
   const long long s = *base + offset;
   const int k = tiles.member[tile];
+  if (k < 0) return;
   const int local = tiles.local[tile];
   const BatchMember mb = mem[k];
   if (s < mb.s_begin || s >= mb.s_end) return;

@@ -1,16 +1,18 @@
 // ka_batch_host.cpp -- host side of batched execution (include/ka.h, "Batches").
 //
-// A batch keeps a member table (pinned host copy + device copy), a device step base, and
-// per segment (a run of steps with a fixed set of active members) a tile table built on the
+// A batch keeps a member table (host copy + device copy), a device step base, and per
+// segment (a run of steps with a fixed set of active members) a tile table built on the
 // device.  The host cuts the steps it enqueues into segments at the steps where members
 // finish or join, enqueues whole captured graphs of "G step kernels + base += G" and single
 // launches for the rest.  Progress events let ka_batch_poll detach finished members without
-// blocking.  Member descriptors never change while a member is active, and a slot is reused
-// only after its member's last step has completed on the device, so one pinned table and
-// whole-table asynchronous uploads are enough: a table that already holds members added
-// later is still correct for earlier steps, because a member is inactive outside
-// [s_begin, s_end).  Tile tables alternate between two device buffers; stream order puts
-// each rebuild after every step that read the buffer before.
+// blocking.  A slot is reused only after its member's last step has completed on the device.
+// Each upload of the member table goes through one of a ring of pinned staging copies,
+// which the host rewrites only after that copy's previous upload has completed (an event):
+// the DMA reads pinned memory when it executes, not when it is enqueued, so the host table
+// itself (changed by later adds and by workgroup-size changes) is never read by a pending
+// upload.
+// Tile tables alternate between two device buffers; stream order puts each rebuild after
+// every step that read the buffer before.
 #include <algorithm>
 #include <cstdarg>
 #include <cstdio>
@@ -63,7 +65,11 @@ struct ka_batch {
   bool own_stream = false;
   int capacity = 0;
   int cus = 256;
-  ka::BatchMember *host_tab = nullptr;   // pinned
+  std::vector<ka::BatchMember> tab;      // host member table, per slot
+  static constexpr int kStages = 4;
+  ka::BatchMember *stage[kStages] = {};   // pinned staging copies for uploads
+  hipEvent_t stage_ev[kStages] = {};      // completion of each copy's last upload
+  int stage_next = 0;
   ka::BatchMember *d_tab = nullptr;
   long long *d_base = nullptr;           // device step base
   int *d_total = nullptr;
@@ -111,7 +117,7 @@ hipEvent_t take_event(ka_batch *b)
 
 int tiles_per_plane(const ka_batch *b, int k, int block)
 {
-  const ka::BatchMember &m = b->host_tab[k];
+  const ka::BatchMember &m = b->tab[(size_t)k];
   if (m.kind == 0) {
     const int nsub = m.d == 2 ? 4 : 16;
     const int threads = nsub * 64 * ((m.P + 63) / 64);
@@ -124,7 +130,7 @@ int tiles_per_plane(const ka_batch *b, int k, int block)
 
 bool active_at(const ka_batch *b, int k, int64_t s)
 {
-  return b->sims[(size_t)k] && b->host_tab[k].s_begin <= s && s < b->host_tab[k].s_end;
+  return b->sims[(size_t)k] && b->tab[(size_t)k].s_begin <= s && s < b->tab[(size_t)k].s_end;
 }
 
 void drop_graph(ka_batch::Graph &g)
@@ -159,10 +165,16 @@ hipError_t new_segment(ka_batch *b)
   hipError_t e = hipSuccess;
   if (b->dirty) {
     for (int k = 0; k < b->n_members; ++k)
-      if (b->sims[(size_t)k]) b->host_tab[k].tiles_per_plane = tiles_per_plane(b, k, b->block);
-    e = hipMemcpyAsync(b->d_tab, b->host_tab, sizeof(ka::BatchMember) * (size_t)std::max(1, b->n_members),
-                       hipMemcpyHostToDevice, b->stream);
+      if (b->sims[(size_t)k]) b->tab[(size_t)k].tiles_per_plane = tiles_per_plane(b, k, b->block);
+    const int q = b->stage_next;
+    e = hipEventSynchronize(b->stage_ev[q]);   // this copy's previous upload has been read
     if (e != hipSuccess) return e;
+    const size_t bytes = sizeof(ka::BatchMember) * (size_t)std::max(1, b->n_members);
+    std::memcpy(b->stage[q], b->tab.data(), bytes);
+    e = hipMemcpyAsync(b->d_tab, b->stage[q], bytes, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->stage_ev[q], b->stream);
+    if (e != hipSuccess) return e;
+    b->stage_next = (q + 1) % ka_batch::kStages;
     b->dirty = false;
   }
   const int64_t S = b->step;
@@ -170,7 +182,7 @@ hipError_t new_segment(ka_batch *b)
   int64_t end = INT64_MAX;
   for (int k = 0; k < b->n_members; ++k) {
     if (!active_at(b, k, S)) continue;
-    const ka::BatchMember &m = b->host_tab[k];
+    const ka::BatchMember &m = b->tab[(size_t)k];
     T[m.wpt - 1] += m.planes * m.tiles_per_plane;
     end = std::min<int64_t>(end, m.s_end);
   }
@@ -180,7 +192,7 @@ hipError_t new_segment(ka_batch *b)
     if (T[w] == 0) continue;
     e = grow(b, b->buf, w, T[w]);
     if (e == hipSuccess) {
-      ka::BatchTiles tt{b->d_tmember[b->buf][w], b->d_tlocal[b->buf][w]};
+      ka::BatchTiles tt{b->d_tmember[b->buf][w], b->d_tlocal[b->buf][w], T[w]};
       e = ka::launch_batch_prepare(b->d_tab, b->n_members, S, w + 1, tt, b->d_total, b->stream);
     }
   }
@@ -195,7 +207,7 @@ hipError_t launch_steps(ka_batch *b, int count)
   for (int q = 0; q < count && e == hipSuccess; ++q)
     for (int w = 0; w < 2 && e == hipSuccess; ++w)
       if (b->T[w] > 0) {
-        ka::BatchTiles tt{b->d_tmember[b->buf][w], b->d_tlocal[b->buf][w]};
+        ka::BatchTiles tt{b->d_tmember[b->buf][w], b->d_tlocal[b->buf][w], b->T[w]};
         e = ka::launch_batch_step(b->d_tab, tt, b->T[w], b->d_base, q, b->block, w + 1, b->stream);
       }
   if (e == hipSuccess) e = ka::launch_batch_advance(b->d_base, count, b->stream);
@@ -270,7 +282,7 @@ int64_t max_classes(const ka_batch *b)
 {
   int64_t c = 1;
   for (int k = 0; k < b->n_members; ++k)
-    if (b->sims[(size_t)k] && b->host_tab[k].s_end > b->step) c = std::max<int64_t>(c, b->host_tab[k].C);
+    if (b->sims[(size_t)k] && b->tab[(size_t)k].s_end > b->step) c = std::max<int64_t>(c, b->tab[(size_t)k].C);
   return c;
 }
 
@@ -362,17 +374,21 @@ extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
       e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
       b->own_stream = e == hipSuccess;
     }
-    if (e == hipSuccess) e = hipHostMalloc((void **)&b->host_tab, sizeof(ka::BatchMember) * (size_t)capacity, hipHostMallocDefault);
+    b->tab.assign((size_t)capacity, ka::BatchMember{});
+    for (int q = 0; q < ka_batch::kStages && e == hipSuccess; ++q) {
+      e = hipHostMalloc((void **)&b->stage[q], sizeof(ka::BatchMember) * (size_t)capacity, hipHostMallocDefault);
+      if (e == hipSuccess) e = hipEventCreateWithFlags(&b->stage_ev[q], hipEventDisableTiming);
+    }
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_tab, sizeof(ka::BatchMember) * (size_t)capacity);
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_base, sizeof(long long));
     if (e == hipSuccess) e = hipMalloc((void **)&b->d_total, sizeof(int));
-    if (e == hipSuccess) {
-      std::memset(b->host_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity);
-      e = hipMemsetAsync(b->d_base, 0, sizeof(long long), b->stream);
-    }
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_base, 0, sizeof(long long), b->stream);
     if (e == hipSuccess) e = hipMemsetAsync(b->d_tab, 0, sizeof(ka::BatchMember) * (size_t)capacity, b->stream);
     if (e != hipSuccess) {
-      if (b->host_tab) (void)hipHostFree(b->host_tab);
+      for (int q = 0; q < ka_batch::kStages; ++q) {
+        if (b->stage[q]) (void)hipHostFree(b->stage[q]);
+        if (b->stage_ev[q]) (void)hipEventDestroy(b->stage_ev[q]);
+      }
       (void)hipFree(b->d_tab);
       (void)hipFree(b->d_base);
       (void)hipFree(b->d_total);
@@ -435,7 +451,7 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
     b->class_sizes[(size_t)k].clear();
     if (!s->lattice)
       for (int c = 0; c < s->C; ++c) b->class_sizes[(size_t)k].push_back(s->plan->class_start[(size_t)c + 1] - s->plan->class_start[(size_t)c]);
-    b->host_tab[k] = m;
+    b->tab[(size_t)k] = m;
     b->sims[(size_t)k] = s;
     b->sweeps[(size_t)k] = n_sweeps;
     b->n_members = std::max(b->n_members, k + 1);
@@ -466,7 +482,7 @@ extern "C" int ka_batch_steps_left(const ka_batch *b, int64_t *steps_left)
     if (!b || !steps_left) return bfail(KA_EINVAL, "NULL argument");
     int64_t left = 0;
     for (int k = 0; k < b->n_members; ++k)
-      if (b->sims[(size_t)k]) left = std::max<int64_t>(left, b->host_tab[k].s_end - b->step);
+      if (b->sims[(size_t)k]) left = std::max<int64_t>(left, b->tab[(size_t)k].s_end - b->step);
     *steps_left = left;
     return KA_OK;
   });
@@ -480,7 +496,7 @@ extern "C" int ka_batch_poll(ka_batch *b, int *slots, int max_slots, int *n_done
     harvest(b);
     int got = 0;
     for (int k = 0; k < b->n_members; ++k) {
-      if (!b->sims[(size_t)k] || b->host_tab[k].s_end > b->done_step) continue;
+      if (!b->sims[(size_t)k] || b->tab[(size_t)k].s_end > b->done_step) continue;
       if (slots && got >= max_slots) break;
       detach(b, k);
       if (slots) slots[got] = k;
@@ -564,7 +580,10 @@ extern "C" void ka_batch_free(ka_batch *b)
         (void)hipFree(b->d_tmember[q][w]);
         (void)hipFree(b->d_tlocal[q][w]);
       }
-    (void)hipHostFree(b->host_tab);
+    for (int q = 0; q < ka_batch::kStages; ++q) {
+      (void)hipHostFree(b->stage[q]);
+      (void)hipEventDestroy(b->stage_ev[q]);
+    }
     (void)hipFree(b->d_tab);
     (void)hipFree(b->d_base);
     (void)hipFree(b->d_total);

@@ -170,10 +170,13 @@ struct BatchMember {
 };
 
 // Work list of one segment (steps between membership changes): tile q belongs to member
-// tile_member[q] as its tile tile_local[q].  Built on the device by the prepare kernel.
+// member[q] as its tile local[q].  Built on the device by the prepare kernel; cap is the
+// number of entries the host sized the buffers for and launches step kernels over (entries
+// past the device's own total hold member -1, and none is written at or past cap).
 struct BatchTiles {
   int *member;
   int *local;
+  int cap;
 };
 
 hipError_t launch_batch_prepare(const BatchMember *mem, int n_members, long long step, int wpt,
