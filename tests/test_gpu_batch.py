@@ -104,6 +104,32 @@ def test_batch_members_equal_solo(graphs, solo, options):
     assert info[1] == 0  # all members detached
 
 
+def test_block_changes_between_queued_runs(graphs, solo):
+    """The workgroup size changes between ka_batch_run calls while earlier steps (and the
+    member-table uploads enqueued with them) are still pending on the stream: each upload
+    must carry the table of its own segment, so every member still ends in its solo state."""
+    _say("batch: block changes with queued work")
+    b = ka.ka_batch_create(64)
+    ka.ka_batch_set_option(b, ka.KA_BOPT_GRAPH_STEPS, 2)
+    sims = []
+    for spec, g in zip(MEMBERS, graphs):
+        s = _make(spec, g)
+        ka.ka_batch_add(b, s, spec[7])
+        sims.append(s)
+    blocks = [128, 512, 256, 512, 128, 256]
+    q = 0
+    while ka.ka_batch_steps_left(b) > 0:
+        ka.ka_batch_set_option(b, ka.KA_BOPT_BLOCK, blocks[q % len(blocks)])
+        ka.ka_batch_run(b, 3)
+        q += 1
+    ka.ka_batch_wait_all(b)
+    states = [ka.ka_get_state(s) for s in sims]
+    b.free()
+    _assert_same(states, solo)
+    for s in sims:
+        s.free()
+
+
 def test_batch_members_match_oracle(oracle):
     """Two members checked against the oracle directly (all replicas, state and counts)."""
     g2 = ka.ka_graph_lattice(2, 12)
