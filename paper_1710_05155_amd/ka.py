@@ -48,6 +48,8 @@ class JobDesc(ctypes.Structure):
         ("n_obs", ctypes.c_int),
         ("keep_sim", ctypes.c_int),
     ]
+
+
 KA_BOPT_AUTOTUNE = 1
 KA_BOPT_BLOCK = 2
 KA_BOPT_GRAPH_STEPS = 4
