@@ -39,6 +39,10 @@
  *     pairing on any self-loop or multi-edge (Sec. 2.1, Bollobas' construction);
  *   - edge classes: on lattices 4*mu + ((x_mu + 2*sum_{nu!=mu} x_nu) mod 4); on general
  *     graphs the greedy distance-2 ("strong") edge colouring in canonical edge order.
+ *
+ * The paper's own random-sequential algorithm (one random particle and neighbour per
+ * attempt) is here too (ko_rs_run), for statistical cross-checks of the class schedule
+ * only; no parity test uses it.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -437,6 +441,90 @@ int ko_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------------------ */
+/* Random-sequential dynamics: the paper's own algorithm (Sec. 2.1), kept for            */
+/* statistical cross-checks of the class schedule, never for parity.  One attempt picks  */
+/* a particle uniformly among the K, then one of its z neighbours uniformly; the particle */
+/* at i moves to j iff (a) j is empty, (b) i has at most m occupied neighbours and (c) j  */
+/* has at most m+1 occupied neighbours (i, occupied, counted among them).                */
+/* Attempt a of replica b draws Philox with counter (b, 0xFFFFFFFC, a low, a high) and    */
+/* key seed: words 0|1<<32 choose the particle, words 2|3<<32 the neighbour slot, each by */
+/* the multiply-shift floor(u * range / 2^64) of the 64-bit word (bias below range/2^64). */
+/* The particle with index p is the p-th occupied site in increasing site order, so a     */
+/* run split into several calls draws the same moves as one call.                         */
+/* ------------------------------------------------------------------------------------ */
+
+/* Target site of the attempt "particle at i, neighbour slot k" in occ, or -1 if the move
+ * is not allowed (or i is empty). */
+int64_t ko_rs_target(int z, int m, const int32_t *adj, const uint8_t *occ, int64_t i, int k)
+{
+    if (!occ[i]) return -1;
+    int64_t j = adj[i * z + k];
+    if (occ[j]) return -1;                                   /* (a) */
+    int count_i = 0, count_j = 0;
+    for (int q = 0; q < z; ++q) {
+        count_i += occ[adj[i * z + q]];
+        count_j += occ[adj[j * z + q]];
+    }
+    return (count_i <= m && count_j <= m + 1) ? j : -1;     /* (b), (c) */
+}
+
+/* ko_rs_target for every state row (n_states x N), site i and slot k: out is
+ * n_states x N x z. */
+void ko_rs_targets(int64_t N, int z, const int32_t *adj, int m, int64_t n_states,
+                   const uint8_t *occ, int64_t *out)
+{
+    for (int64_t s = 0; s < n_states; ++s)
+        for (int64_t i = 0; i < N; ++i)
+            for (int k = 0; k < z; ++k)
+                out[(s * N + i) * z + k] = ko_rs_target(z, m, adj, occ + s * N, i, k);
+}
+
+static uint64_t ko_rs_pick(uint32_t lo, uint32_t hi, uint64_t range)
+{
+    unsigned __int128 u = (unsigned __int128)(((uint64_t)hi << 32) | lo);
+    return (uint64_t)((u * range) >> 64);
+}
+
+/* Attempts a0 .. a0+n_attempts-1 of the replicas reps[0..nrep-1]; occ and moved are
+ * nrep*N, row q belonging to replica reps[q].  Every row must hold K >= 1 particles. */
+void ko_rs_run(int64_t N, int z, const int32_t *adj, int m, uint64_t seed, int64_t nrep,
+               const int64_t *reps, uint64_t a0, uint64_t n_attempts, uint8_t *occ,
+               uint8_t *moved)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nrep; ++q) {
+        uint8_t *o = occ + q * N, *mv = moved + q * N;
+        /* occupied sites in increasing order */
+        int64_t *part = (int64_t *)malloc(sizeof(int64_t) * (N > 0 ? N : 1));
+        int64_t K = 0;
+        for (int64_t i = 0; i < N; ++i)
+            if (o[i]) part[K++] = i;
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        for (uint64_t a = a0; K > 0 && a < a0 + n_attempts; ++a) {
+            uint32_t ctr[4] = {(uint32_t)reps[q], 0xFFFFFFFCu, (uint32_t)a, (uint32_t)(a >> 32)};
+            uint32_t w[4];
+            ko_philox(ctr, key, w);
+            int64_t p = (int64_t)ko_rs_pick(w[0], w[1], (uint64_t)K);
+            int k = (int)ko_rs_pick(w[2], w[3], (uint64_t)z);
+            int64_t i = part[p];
+            int64_t j = ko_rs_target(z, m, adj, o, i, k);
+            if (j < 0) continue;
+            o[i] = 0;
+            o[j] = 1;
+            mv[i] = 1;
+            mv[j] = 1;
+            /* keep part sorted: drop i at position p, insert j */
+            memmove(part + p, part + p + 1, sizeof(int64_t) * (size_t)(K - 1 - p));
+            int64_t pos = 0;
+            while (pos < K - 1 && part[pos] < j) ++pos;
+            memmove(part + pos + 1, part + pos, sizeof(int64_t) * (size_t)(K - 1 - pos));
+            part[pos] = j;
+        }
+        free(part);
+    }
 }
 
 /* ------------------------------------------------------------------------------------ */

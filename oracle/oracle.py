@@ -55,6 +55,8 @@ def load():
         _lib.ko_layered.argtypes = [I32, I32, I32, U64, P]
         _lib.ko_layered.restype = I32
         _lib.ko_layered_classes.argtypes = [I32, I32, I64, I64, P, P, P]
+        _lib.ko_rs_targets.argtypes = [I64, I32, P, I32, I64, P, P]
+        _lib.ko_rs_run.argtypes = [I64, I32, P, I32, U64, I64, P, U64, U64, P, P]
     return _lib
 
 
@@ -231,6 +233,31 @@ def threads() -> int:
     return int(load().ko_threads())
 
 
+# ----------------------------------------------------------------------------- random sequential
+def rs_targets(g: Graph, m: int, occ: np.ndarray) -> np.ndarray:
+    """Paper's random-sequential rule (Sec. 2.1 (a)-(c)) for every state row of occ
+    (n, N), site i and neighbour slot k: the target site of the move, or -1."""
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    n = occ.shape[0]
+    out = np.empty((n, g.N, g.z), dtype=np.int64)
+    load().ko_rs_targets(g.N, g.z, _p(g.adj), m, n, _p(occ), _p(out))
+    return out
+
+
+def rs_run(g: Graph, m: int, seed: int, replicas, occ: np.ndarray, moved: np.ndarray,
+           a0: int, n_attempts: int) -> None:
+    """Random-sequential attempts a0 .. a0+n_attempts-1 in place (rows = listed replicas):
+    a uniform particle, a uniform neighbour, the move made if rules (a)-(c) allow it.
+    For statistical cross-checks only; its time unit is attempts (K attempts = one
+    attempt per particle)."""
+    lib = load()
+    reps = np.ascontiguousarray(np.asarray(list(replicas), dtype=np.int64))
+    assert occ.shape == (reps.shape[0], g.N) and moved.shape == occ.shape
+    assert occ.flags["C_CONTIGUOUS"] and moved.flags["C_CONTIGUOUS"]
+    lib.ko_rs_run(g.N, g.z, _p(g.adj), m, seed, reps.shape[0], _p(reps), int(a0),
+                  int(n_attempts), _p(occ), _p(moved))
+
+
 # ----------------------------------------------------------------------------- observables
 def observe(occ: np.ndarray, occ0: np.ndarray, moved: np.ndarray):
     """Per-replica integer counts (Sec. 2.2 overlap q_i = n_i(t) n_i(0); Sec. 3.3):
@@ -296,6 +323,27 @@ class Sim:
         if n > 0:
             run(self.g, self.m, self.seed, self.replicas, self.occ, self.moved, self.t, n,
                 self.shared)
+            self.t += n
+
+    def observe(self):
+        return observe(self.occ, self.occ0, self.moved)
+
+
+class RSim:
+    """Replicas of one (graph, m, K, seed) under the random-sequential dynamics, started
+    from the same initial states as Sim; t counts attempts."""
+
+    def __init__(self, g: Graph, m: int, K: int, seed: int, replicas):
+        self.g, self.m, self.K, self.seed = g, m, int(K), seed
+        self.replicas = [int(b) for b in replicas]
+        self.occ = init(g, K, seed, self.replicas)
+        self.occ0 = self.occ.copy()
+        self.moved = np.zeros_like(self.occ)
+        self.t = 0
+
+    def attempt(self, n: int) -> None:
+        if n > 0:
+            rs_run(self.g, self.m, self.seed, self.replicas, self.occ, self.moved, self.t, n)
             self.t += n
 
     def observe(self):
