@@ -183,8 +183,9 @@ int ka_timing(ka_sim *s, int64_t *launches, int64_t *timed, double *timed_ms);
 /* Path a ka_sweep would take now: 1 = global class passes, 2 = LDS-resident. */
 int ka_sim_path(const ka_sim *s, int *path);
 
-/* Release a sim.  A sim that is still a batch member is first run to the end of its
- * batch work (see ka_batch_add). */
+/* Release a sim.  If the sim is still a batch member, its batch is first run to completion
+ * (as ka_batch_wait_all, which detaches every member), so the member's device work never
+ * outlives its memory. */
 void ka_free(ka_sim *s);
 
 /* ------------------------------------------------------------------------------------ */
