@@ -14,7 +14,10 @@ unit).  Also reported: the rate without the observations, and the roofline of th
 kernel (the global-memory class pass).  Its average launch time is the HIP-event stream time
 of the timed jobs' sweep loops, less the same number of observations timed on their own,
 divided by the number of class-pass launches; so it includes the short gaps between
-back-to-back launches.  Last, the oracle's rate on a bounded sample on this host's cores.
+back-to-back launches.  With --plane-streams a sim with two or more word planes runs them as
+separate launches on two streams that overlap, and this figure is each launch's share of the
+wall time (the launches' own durations overlap and are longer).  Last, the oracle's rate on
+a bounded sample on this host's cores.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload cubic128]
 """
@@ -379,6 +382,9 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that a "
                          "hardware-counter run can scale HBM byte counters by a kernel of known traffic")
+    ap.add_argument("--plane-streams", action="store_true",
+                    help="lattice workloads: run the word planes on two streams of each sim's own "
+                         "(KA_OPT_PLANE_STREAMS=1) instead of one launch per class pass")
     ap.add_argument("--no-serial", action="store_true", help="batch workload: skip the one-at-a-time baseline")
     ap.add_argument("--replicas", type=int, default=None, help="override the replica count (exploration only)")
     ap.add_argument("--jobs", type=int, default=200, help="serve workload: jobs in the trace")
@@ -453,6 +459,8 @@ def main():
         sim = ka.ka_init(g, w["m"], rho, 1, R, stream=stream)
         if args.timing_every > 0:
             ka.ka_set_option(sim, ka.KA_OPT_TIMING, args.timing_every)
+        if args.plane_streams:
+            ka.ka_set_option(sim, ka.KA_OPT_PLANE_STREAMS, 1)
         if timed:
             evs = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
             evs[0].record(stream)
@@ -522,7 +530,8 @@ def main():
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": w["desc"], "sites": N, "replicas": R, "sweeps_per_step": sweeps,
-                   "observations_per_step": len(grid), "path": {1: "global class passes", 2: "LDS-resident"}[path]},
+                   "observations_per_step": len(grid), "path": {1: "global class passes", 2: "LDS-resident"}[path],
+                   "plane_streams": bool(args.plane_streams)},
         "edge_replica_updates_per_s": edges * R * sweeps * args.steps / wall,
         "stream_event_ms": gpu_ms,
         "rate_excluding_observe": attempts / (sweep_ms / 1000.0) if path == 1 else None,
@@ -535,12 +544,17 @@ def main():
         B = graph_bytes_model(adj, eu, ev, ec, g.C, g.z, W) / g.C
         kernel = "k_pass_graph"
     if path == 1 and pass_launches > 0 and B:
+        # B is one class step over all word planes; a lattice sim with two or more planes
+        # launches one kernel per plane and class step (on two streams, overlapping), so the
+        # bytes of one launch are the step's bytes over the launches per step
+        class_steps = sweeps * g.C * args.steps
+        B = B * class_steps / pass_launches
         avg_s = sweep_ms / pass_launches / 1000.0
         achieved = B / avg_s / 1e9
         csrc = os.path.join(ROOT, "paper_1710_05155_amd", "csrc")
         traffic = None
         valu = None
-        if args.workload == "cubic128" and R == 256:
+        if args.workload == "cubic128" and R == 256 and not args.plane_streams:
             srcs = [os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")]
             cfile = os.path.join(ROOT, "profiles", "k_pass_lattice_cubic128.counters.txt")
             traffic = measured_traffic(srcs, cfile)

@@ -170,14 +170,25 @@ int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t *K, int *m
  *                      bit 0 of output word 0 of Philox(t, c, e, 0xFFFFFFFF).  This is the
  *                      paper's multispin step (Sec. 3.2), which applies one random choice to
  *                      all replicas of a word.  Replicas are then coupled: replicas started
- *                      equal stay equal.  Applies to the sweeps that follow. */
+ *                      equal stay equal.  Applies to the sweeps that follow.
+ *   KA_OPT_PLANE_STREAMS: 0 (default) = every word plane in one launch per class pass on
+ *                  the sim's stream; 1 = on the global-memory path, a lattice sim with two
+ *                  or more word planes (independent replica chains) runs even planes on one
+ *                  stream of its own and odd planes on another, forked from and joined back
+ *                  to the sim's stream, so that one plane's pass overlaps the start and end
+ *                  of the other's.  The overlap needs the runtime to place the two streams
+ *                  on different hardware queues; on a shared queue the passes serialize and
+ *                  run slower.  Not used while KA_OPT_TIMING is on.  Results are identical
+ *                  either way. */
 #define KA_OPT_PATH 1
 #define KA_OPT_TIMING 2
 #define KA_OPT_NOISE 3
+#define KA_OPT_PLANE_STREAMS 4
 int ka_set_option(ka_sim *s, int option, int64_t value);
 
-/* Class-pass launches so far, and among them the number bracketed by events and their
- * summed duration in milliseconds (synchronises the stream). */
+/* Class-pass kernel launches so far (one per class step, or one per word plane and class
+ * step when the planes run on their own streams), and among them the number bracketed by
+ * events and their summed duration in milliseconds (synchronises the stream). */
 int ka_timing(ka_sim *s, int64_t *launches, int64_t *timed, double *timed_ms);
 
 /* Path a ka_sweep would take now: 1 = global class passes, 2 = LDS-resident. */

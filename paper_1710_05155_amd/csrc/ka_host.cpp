@@ -567,8 +567,48 @@ void harvest_timing(ka_sim *s)
   s->pending.clear();
 }
 
-// One class pass over global memory.
-hipError_t launch_class(ka_sim *s, int c, uint32_t t)
+// Release the sim's plane streams and their events (after the sim's stream has been
+// synchronised, which waits for their work through the join events).
+void release_plane_streams(ka_sim *s)
+{
+  for (int k = 0; k < 2; ++k) {
+    if (s->plane_stream[k]) {
+      (void)hipStreamSynchronize(s->plane_stream[k]);
+      (void)hipStreamDestroy(s->plane_stream[k]);
+    }
+    if (s->join_ev[k]) (void)hipEventDestroy(s->join_ev[k]);
+    s->plane_stream[k] = nullptr;
+    s->join_ev[k] = nullptr;
+  }
+  if (s->fork_ev) (void)hipEventDestroy(s->fork_ev);
+  s->fork_ev = nullptr;
+}
+
+// Whether the sweeps about to be enqueued run the word planes on the sim's two plane
+// streams (KA_OPT_PLANE_STREAMS); creates them on first use and falls back to the sim's
+// stream alone if that fails.
+bool plane_split(ka_sim *s)
+{
+  if (!s->lattice || s->planes < 2 || !s->plane_streams || s->timing_every > 0) return false;
+  if (s->plane_stream[0]) return true;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipStreamCreateWithFlags(&s->plane_stream[k], hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork_ev, hipEventDisableTiming);
+  for (int k = 0; k < 2 && e == hipSuccess; ++k)
+    e = hipEventCreateWithFlags(&s->join_ev[k], hipEventDisableTiming);
+  if (e != hipSuccess) {
+    release_plane_streams(s);
+    (void)hipGetLastError();
+    s->plane_streams = 0;
+    return false;
+  }
+  return true;
+}
+
+// One class pass over global memory: one launch over all planes on the sim's stream, or
+// with `split` one launch per plane on the plane streams.
+hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
 {
   const uint32_t k0 = (uint32_t)s->seed, k1 = (uint32_t)(s->seed >> 32);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -594,6 +634,17 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t)
     a.key0 = k0;
     a.key1 = k1;
     a.noise = s->noise;
+    if (split) {
+      err = hipSuccess;
+      for (int p = 0; p < s->planes && err == hipSuccess; ++p) {
+        a.plane0 = p;
+        a.planes = 1;
+        err = ka::launch_pass_lattice(a, s->m, s->wpt, s->plane_stream[p & 1]);
+        s->launches += 1;
+      }
+      return err;
+    }
+    a.plane0 = 0;
     err = ka::launch_pass_lattice(a, s->m, s->wpt, s->stream);
   } else {
     ka::PassGraph a{};
@@ -674,14 +725,28 @@ hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
 
 hipError_t sweep_global(ka_sim *s, int64_t n)
 {
-  for (int64_t q = 0; q < n; ++q) {
+  if (n <= 0) return hipSuccess;
+  const bool split = plane_split(s);
+  hipError_t e = hipSuccess;
+  if (split) {
+    e = hipEventRecord(s->fork_ev, s->stream);
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(s->plane_stream[k], s->fork_ev, 0);
+    if (e != hipSuccess) return e;
+  }
+  for (int64_t q = 0; q < n && e == hipSuccess; ++q) {
     const uint32_t t = (uint32_t)(s->t + q);
-    for (int c = 0; c < s->C; ++c) {
-      hipError_t e = launch_class(s, c, t);
-      if (e != hipSuccess) return e;
+    for (int c = 0; c < s->C && e == hipSuccess; ++c) e = launch_class(s, c, t, split);
+  }
+  if (split) {
+    // joined even after a failed launch, so that later work on the sim's stream stays
+    // ordered after everything the plane streams received
+    for (int k = 0; k < 2; ++k) {
+      hipError_t j = hipEventRecord(s->join_ev[k], s->plane_stream[k]);
+      if (j == hipSuccess) j = hipStreamWaitEvent(s->stream, s->join_ev[k], 0);
+      if (e == hipSuccess) e = j;
     }
   }
-  return hipSuccess;
+  return e;
 }
 
 hipError_t observe_global(ka_sim *s, int row)
@@ -1335,6 +1400,11 @@ extern "C" int ka_set_option(ka_sim *s, int option, int64_t value)
       s->noise = (int)value;
       return KA_OK;
     }
+    if (option == KA_OPT_PLANE_STREAMS) {
+      if (value != 0 && value != 1) return fail(KA_EINVAL, "plane streams must be 0 or 1");
+      s->plane_streams = (int)value;
+      return KA_OK;
+    }
     return fail(KA_EINVAL, "unknown option %d", option);
   });
 }
@@ -1370,6 +1440,7 @@ extern "C" void ka_free(ka_sim *s)
     if (s->batch) (void)ka_batch_release_member(s->batch, s);
     DeviceGuard dg(s->device);
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    release_plane_streams(s);
     harvest_timing(s);
     for (hipEvent_t ev : s->event_pool) (void)hipEventDestroy(ev);
     free_device(s);

@@ -43,7 +43,8 @@ struct PassLattice {
   LatticeGeom g;
   int mu;
   int noise;                 // 0: acceptance bit per replica, 1: shared by all replicas
-  int planes;
+  int planes;                // planes in this launch
+  int plane0;                // first plane of this launch
   int blocks_per_plane;
   uint32_t t, c, key0, key1;
 };

@@ -52,6 +52,11 @@ struct ka_sim {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // word planes on streams of their own (lattices, global path): even planes on
+  // plane_stream[0], odd ones on plane_stream[1], forked from and joined to `stream`
+  hipStream_t plane_stream[2] = {nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[2] = {nullptr, nullptr};
   // device memory
   ka::u64 *n = nullptr, *n0 = nullptr, *f = nullptr;
   int32_t *nbr = nullptr;             // graphs: [2(z-1)][E] neighbour lists of the records
@@ -72,6 +77,7 @@ struct ka_sim {
   bool init_checked = false;
   int path_opt = 0;
   int noise = 0;                  // KA_OPT_NOISE
+  int plane_streams = 0;          // KA_OPT_PLANE_STREAMS
   size_t lds_bytes = 0;
   bool lds_fits = false;
   int64_t timing_every = 0;

@@ -17,7 +17,7 @@ constexpr int kGraphSmallBlock = 64;
 constexpr long long kGraphSmallEdges = 65536;
 
 // ------------------------------------------------------------------------------------
-// Global-memory class pass kernels: one launch per (class, sweep), all planes at once.
+// Global-memory class pass kernels: one launch per (class, sweep) over a range of planes.
 // ------------------------------------------------------------------------------------
 // Thread order: a wave covers 64 consecutive positions of one lower-endpoint sublattice
 // (coalesced 64 x 16 B loads); consecutive waves cover the class's other lower-endpoint
@@ -27,8 +27,9 @@ template <int D, int MU, int WPT>
 __global__ __launch_bounds__(kPassBlock) void k_pass_lattice(PassLattice a, int m)
 {
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int plane = lin / a.blocks_per_plane;
-  const int blk = lin - plane * a.blocks_per_plane;
+  const int pl = lin / a.blocks_per_plane;
+  const int blk = lin - pl * a.blocks_per_plane;
+  const int plane = a.plane0 + pl;
   const int gid = blk * kPassBlock + (int)threadIdx.x;
   constexpr int nsub = D == 2 ? 4 : 16;   // lower-endpoint sublattices per class
   const int span = nsub * 64;              // threads per 64-position chunk

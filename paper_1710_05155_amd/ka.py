@@ -21,6 +21,7 @@ KA_ESTATE = -4
 KA_OPT_PATH = 1
 KA_OPT_TIMING = 2
 KA_OPT_NOISE = 3
+KA_OPT_PLANE_STREAMS = 4
 
 # Every symbol include/ka.h declares.
 SYMBOLS = (

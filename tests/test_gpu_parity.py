@@ -180,6 +180,41 @@ def test_paths_agree_and_split_invariance(oracle):
         assert np.array_equal(np.asarray(x), np.asarray(y))
 
 
+@pytest.mark.parametrize("d,L,R", [(3, 12, 256), (2, 16, 192), (2, 16, 320)])
+def test_plane_streams_identical(oracle, d, L, R):
+    """Word planes on two streams of the sim's own (KA_OPT_PLANE_STREAMS), all planes in one
+    launch (the default), and the timed mode with plane streams asked for (which keeps one
+    stream) end in the same state; with plane streams every plane and class step is one
+    launch.  A few replicas are also checked against the oracle."""
+    g = ka.ka_graph_lattice(d, L)
+    _say(f"plane streams d={d} L={L} R={R}")
+    states, launches = [], []
+    for opts in ([(ka.KA_OPT_PLANE_STREAMS, 1)], [], [(ka.KA_OPT_PLANE_STREAMS, 1), (ka.KA_OPT_TIMING, 3)]):
+        s = ka.ka_init(g, d, 0.7, 12, R)
+        ka.ka_set_option(s, ka.KA_OPT_PATH, 1)
+        for o, v in opts:
+            ka.ka_set_option(s, o, v)
+        ka.ka_sweep(s, 3)
+        ka.ka_run(s, [4, 6])
+        states.append(ka.ka_get_state(s))
+        launches.append(ka.ka_timing(s)[0])
+        s.free()
+    for other in states[1:]:
+        for x, y in zip(states[0], other):
+            assert np.array_equal(np.asarray(x), np.asarray(y))
+    W = R // 64
+    planes = W // 2 if W % 2 == 0 else W
+    C = 4 * d
+    assert launches == [6 * C * planes, 6 * C, 6 * C]
+    og = oracle.lattice(d, L)
+    orc = oracle.Sim(og, d, oracle.k_from_rho(og.N, 0.7), 12, [0, R - 1])
+    orc.sweep(6)
+    n = states[0][0]
+    for q, b in enumerate([0, R - 1]):
+        row = (n[b // 64] >> np.uint64(b % 64)) & np.uint64(1)
+        assert np.array_equal(row.astype(np.uint8), orc.occ[q])
+
+
 def test_set_state_resume(oracle):
     """Checkpoint/resume: a state put back with ka_set_state continues exactly."""
     g = ka.ka_graph_lattice(2, 12)
