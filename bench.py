@@ -391,8 +391,8 @@ def main():
     ap.add_argument("--rate", type=float, default=200.0, help="serve workload: mean arrivals per second")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; the replica planes of a job shard across GPUs "
-              "with no communication, but multi-GPU runs are not part of it (use --gpus 1).",
+        print("bench.py measures one GPU only (use --gpus 1). The replica planes of a job would shard "
+              "across GPUs with no communication, but no multi-GPU path is implemented.",
               file=sys.stderr)
         sys.exit(2)
 
