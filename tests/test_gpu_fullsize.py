@@ -5,11 +5,12 @@
   compared with the oracle (the whole run is small enough for it).
 - 3D cubic lattice L=128, z=6, m=3, 256 replicas (4 words per site), seed 1, observation on
   the 38-point log grid: replicas {0, 63, 64, 255} (first and last bit of the first and last
-  word) are compared with the oracle bit for bit after the first sweeps; the run then goes
-  on to 10^4 sweeps and properties that hold at any size are checked on every replica.
+  word) are compared with the oracle bit for bit at every grid point up to 31 sweeps; the run
+  then goes on to 10^4 sweeps and properties that hold at any size are checked on every
+  replica.
 - Random regular graph N=2^20, z=4, m=2, graph seed 1, 64 replicas: the library's graph
-  and classes equal the oracle's; replicas {0, 63} are compared after the first sweeps at
-  rho = 0.50 and 0.75; invariants after 10^4 sweeps on every replica.
+  and classes equal the oracle's; replicas {0, 63} are compared at every grid point up to 31
+  sweeps at rho = 0.50 and 0.75; invariants after 10^4 sweeps on every replica.
 """
 import numpy as np
 import pytest
@@ -61,7 +62,7 @@ def test_cubic128_sampled_replicas(oracle, rho):
     og = oracle.lattice(3, 128)
     K = oracle.k_from_rho(og.N, rho)
     grid = ka.log_time_grid(10_000)
-    head = [t for t in grid if t <= 3]
+    head = [t for t in grid if t <= 31]
     sample = [0, 63, 64, 255]
     _say(f"cubic128 rho={rho}: head {head}, sampled replicas {sample}")
     sim = ka.ka_init(g, 3, rho, 1, 256)
@@ -79,7 +80,7 @@ def test_cubic128_sampled_replicas(oracle, rho):
         assert np.array_equal(_replica_bits(n0, b), orc.occ0[k]), b
         assert np.array_equal(_replica_bits(f, b), orc.moved[k]), b
     _say(f"cubic128 rho={rho}: continuing to 10^4 sweeps")
-    rest = [t for t in grid if t > 3]
+    rest = [t for t in grid if t > 31]
     d2, o2, p2 = ka.ka_run(sim, rest)
     _check_invariants(K, np.vstack([dens, d2]), np.vstack([ov, o2]), np.vstack([pers, p2]))
     assert sim.t == 10_000
@@ -96,13 +97,14 @@ def test_rrg20_graph_and_sampled_replicas(oracle):
     assert np.array_equal(eu, og.eu) and np.array_equal(ev, og.ev) and np.array_equal(ec, og.ecls)
     for rho in (0.50, 0.75):
         K = oracle.k_from_rho(N, rho)
-        _say(f"rrg N=2^20 rho={rho}: 3 sweeps, replicas 0 and 63")
+        head = [t for t in ka.log_time_grid(10_000) if t <= 31]
+        _say(f"rrg N=2^20 rho={rho}: {head[-1]} sweeps, replicas 0 and 63")
         sim = ka.ka_init(g, 2, rho, 1, 64)
         assert ka.ka_sim_path(sim) == 1
-        dens, ov, pers = ka.ka_run(sim, [0, 1, 3])
+        dens, ov, pers = ka.ka_run(sim, head)
         n, n0, f, t = ka.ka_get_state(sim)
         orc = oracle.Sim(og, 2, K, 1, [0, 63])
-        for q, tt in enumerate([0, 1, 3]):
+        for q, tt in enumerate(head):
             orc.sweep(tt - orc.t)
             od, oo, op = orc.observe()
             for k, b in enumerate([0, 63]):
@@ -110,7 +112,7 @@ def test_rrg20_graph_and_sampled_replicas(oracle):
         for k, b in enumerate([0, 63]):
             assert np.array_equal(_replica_bits(n, b), orc.occ[k])
             assert np.array_equal(_replica_bits(f, b), orc.moved[k])
-        grid = [t for t in ka.log_time_grid(10_000) if t > 3]
+        grid = [t for t in ka.log_time_grid(10_000) if t > 31]
         d2, o2, p2 = ka.ka_run(sim, grid)
         _check_invariants(K, np.vstack([dens, d2]), np.vstack([ov, o2]), np.vstack([pers, p2]))
         sim.free()
