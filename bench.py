@@ -382,6 +382,9 @@ def main():
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB, so that a "
                          "hardware-counter run can scale HBM byte counters by a kernel of known traffic")
+    ap.add_argument("--calibrate-alu", action="store_true",
+                    help="also time register-only VALU chains (v_xor_b32, v_mad_u64_u32) on the whole "
+                         "device and report their issue rates under \"calibration\"")
     ap.add_argument("--plane-streams", action="store_true",
                     help="lattice workloads: run the word planes on two streams of each sim's own "
                          "(KA_OPT_PLANE_STREAMS=1) instead of one launch per class pass")
@@ -564,6 +567,13 @@ def main():
                               "valu_busy_pct": valu, "kernel": kernel, "avg_launch_us": avg_s * 1e6,
                               "bytes_per_launch": B, "launches": pass_launches,
                               "sampled_launch_us": pass_ms_total / pass_timed * 1000.0 if pass_timed else None}
+    if args.calibrate_alu:
+        cal = {}
+        for kind, name in ((0, "v_xor_b32"), (1, "v_mad_u64_u32")):
+            ips, lops = ka.ka_probe_valu(kind, stream=stream)
+            cal[name] = {"wave_instr_per_s": ips, "lane_ops_per_s": lops}
+            log(f"calibration {name}: {ips:.4g} wave instructions/s, {lops:.4g} lane ops/s")
+        result["calibration"] = cal
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w)

@@ -308,6 +308,18 @@ int ka_server_stats(ka_server *sv, int64_t *jobs_done, double *attempts, int *pe
 /* Stop the worker after the queued jobs complete, and release everything. */
 void ka_server_free(ka_server *sv);
 
+/* ------------------------------------------------------------------------------------ */
+/* Calibration: integer vector-ALU issue rate of this device, for the rooflines of the    */
+/* bit-logic kernels.  kind 0 times chains of 32-bit v_xor_b32, kind 1 chains of           */
+/* v_mad_u64_u32 (the 32 x 32 -> 64-bit multiply-add of the Philox rounds), both from      */
+/* registers only, `iters` loop iterations per thread over `blocks` workgroups of 256      */
+/* threads, on hip_stream (NULL: a stream of its own).  Writes wave-level instructions per */
+/* second and lane operations per second (64 per instruction; may be NULL).  Allocates a   */
+/* small buffer and synchronises the stream.                                               */
+/* ------------------------------------------------------------------------------------ */
+int ka_probe_valu(int kind, int iters, int blocks, void *hip_stream, double *instr_per_s,
+                  double *lane_ops_per_s);
+
 /* Message describing the last error on the calling thread ("" if none). */
 const char *ka_last_error(void);
 

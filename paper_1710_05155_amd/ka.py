@@ -32,7 +32,7 @@ SYMBOLS = (
     "ka_batch_create", "ka_batch_add", "ka_batch_run", "ka_batch_steps_left", "ka_batch_poll",
     "ka_batch_wait_all", "ka_batch_set_option", "ka_batch_info", "ka_batch_free",
     "ka_server_create", "ka_server_submit", "ka_server_poll", "ka_server_result", "ka_server_take_sim", "ka_server_release",
-    "ka_server_wait_idle", "ka_server_stats", "ka_server_free",
+    "ka_server_wait_idle", "ka_server_stats", "ka_server_free", "ka_probe_valu",
 )
 
 
@@ -120,6 +120,7 @@ def load():
         "ka_server_wait_idle": ([P], I),
         "ka_server_stats": ([P, P, P, P, P], I),
         "ka_server_free": ([P], None),
+        "ka_probe_valu": ([I, I, I, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -524,6 +525,19 @@ def ka_server_stats(sv: Server):
 
 def ka_server_free(sv: Server) -> None:
     sv.free()
+
+
+# ------------------------------------------------------------------------------ calibration
+def ka_probe_valu(kind: int, iters: int = 20000, blocks: int = 4096, stream=None):
+    """(wave instructions/s, lane operations/s) of register-only VALU chains: kind 0 =
+    v_xor_b32, kind 1 = v_mad_u64_u32."""
+    ips = ctypes.c_double()
+    lops = ctypes.c_double()
+    rc = load().ka_probe_valu(int(kind), int(iters), int(blocks), _stream_handle(stream), ctypes.byref(ips),
+                              ctypes.byref(lops))
+    if rc != KA_OK:
+        raise KaError(rc, "ka_probe_valu failed")
+    return ips.value, lops.value
 
 
 # ------------------------------------------------------------------------------ host helpers

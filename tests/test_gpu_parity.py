@@ -390,3 +390,15 @@ def test_shared_noise_couples_equal_replicas_on_gpu():
     n, _, _, _ = ka.ka_get_state(sim)
     assert not ((n == np.uint64(0)) | (n == np.uint64(0xFFFFFFFFFFFFFFFF))).all()
     sim.free()
+
+
+def test_valu_probe():
+    """The calibration probe runs, reports positive rates, and rejects bad arguments."""
+    _say("valu probe")
+    for kind in (0, 1):
+        ips, lops = ka.ka_probe_valu(kind, iters=200, blocks=512)
+        assert ips > 0 and lops == pytest.approx(64 * ips)
+    with pytest.raises(ka.KaError):
+        ka.ka_probe_valu(2)
+    with pytest.raises(ka.KaError):
+        ka.ka_probe_valu(0, iters=0)
