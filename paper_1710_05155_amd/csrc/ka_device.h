@@ -340,14 +340,13 @@ __device__ __forceinline__ void lattice_stencil(const LatticeGeom &g, const Site
   }
 }
 
-// The exchange across one edge (i, j) with canonical id e, class c, sweep t, on the plane at
-// base nb (moved-ever words at fb; global memory or LDS), given the element indices of i,
-// j and of their K neighbours other than the partner; shared by every path.
-template <int K, int WPT>
-__device__ __forceinline__ void edge_update(u64 *nb, u64 *fb, int i, int j, const int (&ii)[K],
-                                            const int (&jj)[K], uint32_t e, int plane, int m,
-                                            uint32_t t, uint32_t c, uint32_t k0, uint32_t k1,
-                                            int noise)
+// The exchange across one edge (i, j) on the plane at base nb (moved-ever words at fb;
+// global memory or LDS), given the element indices of i, j and of their K neighbours other
+// than the partner; draw(r) supplies the edge's acceptance words once the state loads are
+// issued.  Shared by every path.
+template <int K, int WPT, typename Draw>
+__device__ __forceinline__ void edge_update_with(u64 *nb, u64 *fb, int i, int j, const int (&ii)[K],
+                                                 const int (&jj)[K], int m, Draw draw)
 {
   Elem<WPT> ni = ld<WPT>(nb, i);
   Elem<WPT> nj = ld<WPT>(nb, j);
@@ -358,7 +357,7 @@ __device__ __forceinline__ void edge_update(u64 *nb, u64 *fb, int i, int j, cons
     xj[k] = ld<WPT>(nb, jj[k]);
   }
   u64 r[WPT];
-  accept_words<WPT>(t, c, e, plane, k0, k1, noise, r);
+  draw(r);
   u64 d[WPT];
   exchange<K, WPT>(ni, nj, xi, xj, r, m, d);
   u64 any = 0;
@@ -382,6 +381,19 @@ __device__ __forceinline__ void edge_update(u64 *nb, u64 *fb, int i, int j, cons
     if (new_i) st<WPT>(fb, i, fi);
     if (new_j) st<WPT>(fb, j, fj);
   }
+}
+
+// The same exchange for the edge with canonical id e, class c, sweep t: its acceptance words
+// are drawn here.
+template <int K, int WPT>
+__device__ __forceinline__ void edge_update(u64 *nb, u64 *fb, int i, int j, const int (&ii)[K],
+                                            const int (&jj)[K], uint32_t e, int plane, int m,
+                                            uint32_t t, uint32_t c, uint32_t k0, uint32_t k1,
+                                            int noise)
+{
+  edge_update_with<K, WPT>(nb, fb, i, j, ii, jj, m, [&](u64 (&r)[WPT]) {
+    accept_words<WPT>(t, c, e, plane, k0, k1, noise, r);
+  });
 }
 
 // Element indices and canonical id of the lattice edge (si, si + e_MU): i, j, the 2D-1

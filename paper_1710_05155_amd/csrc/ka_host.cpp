@@ -496,6 +496,9 @@ void free_device(ka_sim *s)
   (void)hipFree(s->err);
   (void)hipFree(s->counts);
   (void)hipFree(s->obs_d);
+  (void)hipFree(s->lds_acc);
+  s->lds_acc = nullptr;
+  s->lds_acc_sweeps = 0;
   s->n = s->n0 = s->f = nullptr;
 }
 
@@ -672,7 +675,46 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
   return err;
 }
 
-constexpr int64_t kLdsChunk = 20000;  // sweeps per LDS-resident launch
+constexpr int64_t kLdsChunk = 20000;            // sweeps per LDS-resident launch
+constexpr size_t kLdsAccBudget = (size_t)8 << 20;  // bytes of pre-generated acceptance words
+
+// Sweeps per launch and buffer bytes of the pre-generated acceptance words of an LDS lattice
+// sweep (d, L, R); 0 sweeps if that layout draws its words in the loop.
+int64_t lds_acc_plan(int d, int L, int R, size_t *bytes)
+{
+  const int wpt = ((R / 64) % 2 == 0) ? 2 : 1;
+  const int planes = (R / 64) / wpt;
+  if (bytes) *bytes = 0;
+  if (!ka::lds_accept_supported(d, wpt)) return 0;
+  const int Q = L / 4;
+  const int P = d == 2 ? Q * Q : Q * Q * Q;
+  const size_t per_sweep = (size_t)planes * (size_t)(4 * d) * (size_t)ka::lds_lattice_slots(d, P) * 1024u *
+                           (size_t)wpt * 8u;
+  const int64_t sweeps = std::max<int64_t>(1, std::min<int64_t>(kLdsChunk, (int64_t)(kLdsAccBudget / per_sweep)));
+  if (bytes) *bytes = (size_t)sweeps * per_sweep;
+  return sweeps;
+}
+
+// Sweeps per LDS-resident launch of this sim; for a lattice whose layout takes pre-generated
+// acceptance words, allocates their buffer on first use (if that fails, the words are drawn in
+// the loop and launches cover up to kLdsChunk sweeps).
+int64_t lds_chunk(ka_sim *s)
+{
+  if (!s->lattice) return kLdsChunk;
+  if (!s->lds_acc_tried) {
+    s->lds_acc_tried = true;
+    size_t bytes = 0;
+    const int64_t sweeps = lds_acc_plan(s->geom.d, s->geom.L, s->R, &bytes);
+    if (sweeps > 0 && dalloc(&s->lds_acc, bytes) == hipSuccess) {
+      s->lds_acc_sweeps = sweeps;
+    } else {
+      (void)hipGetLastError();
+      s->lds_acc = nullptr;
+      s->lds_acc_sweeps = 0;
+    }
+  }
+  return s->lds_acc ? s->lds_acc_sweeps : kLdsChunk;
+}
 
 hipError_t ensure_obs_buffers(ka_sim *s, size_t n_obs)
 {
@@ -720,6 +762,13 @@ hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
   a.key0 = (uint32_t)s->seed;
   a.key1 = (uint32_t)(s->seed >> 32);
   a.noise = s->noise;
+  if (s->lattice && s->lds_acc && a.n_sweeps > 0) {
+    if (a.n_sweeps > s->lds_acc_sweeps) return hipErrorInvalidValue;
+    a.acc = s->lds_acc;
+    a.acc_slots = ka::lds_lattice_slots(s->geom.d, s->geom.P);
+    hipError_t e = ka::launch_lds_accept(a, s->wpt, s->stream);
+    if (e != hipSuccess) return e;
+  }
   return ka::launch_sweep_lds(a, s->lattice != 0, s->z, s->m, s->wpt, s->lds_bytes, s->stream);
 }
 
@@ -966,6 +1015,14 @@ extern "C" int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_by
     if (n_replicas <= 0 || n_replicas % 64 != 0) return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
     *device_bytes = state_bytes(g->N, n_replicas) + graph_device_bytes(g) +
                     (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u;
+    if (g->lattice) {
+      // an instance on the LDS-resident path adds its pre-generated acceptance words
+      const int wpt = ((n_replicas / 64) % 2 == 0) ? 2 : 1;
+      size_t acc = 0;
+      if (ka::sweep_lds_bytes((int)g->N, wpt) + 4096 <= (size_t)ka::max_lds_bytes())
+        (void)lds_acc_plan(g->d, g->L, n_replicas, &acc);
+      *device_bytes += acc;
+    }
     return KA_OK;
   });
 }
@@ -1113,7 +1170,7 @@ extern "C" int ka_sweep(ka_sim *s, int64_t n_sweeps)
     if (use_lds(s)) {
       int64_t done = 0;
       while (done < n_sweeps && e == hipSuccess) {
-        const int64_t chunk = std::min(kLdsChunk, n_sweeps - done);
+        const int64_t chunk = std::min(lds_chunk(s), n_sweeps - done);
         e = ensure_obs_buffers(s, 1);
         if (e == hipSuccess) e = launch_lds(s, s->t + done, s->t + done + chunk, 0, 0);
         done += chunk;
@@ -1148,13 +1205,14 @@ extern "C" int ka_run(ka_sim *s, const int64_t *obs_times, int n_obs, int64_t *d
     e = hipMemsetAsync(s->counts, 0, cbytes, s->stream);
     if (e == hipSuccess && use_lds(s)) {
       e = hipMemcpyAsync(s->obs_d, obs_times, (size_t)n_obs * sizeof(int64_t), hipMemcpyHostToDevice, s->stream);
-      // chunks [a, b) of at most kLdsChunk sweeps; observation q goes to the first chunk
+      // chunks [a, b) of at most lds_chunk sweeps; observation q goes to the first chunk
       // that can record it (times in [a, b] for the first chunk, (a, b] afterwards)
       int q = 0;
       int64_t a = s->t;
       bool first = true;
+      const int64_t chunk = lds_chunk(s);
       while (e == hipSuccess && q < n_obs) {
-        const int64_t b = std::min(a + kLdsChunk, obs_times[n_obs - 1]);
+        const int64_t b = std::min(a + chunk, obs_times[n_obs - 1]);
         int q1 = q;
         while (q1 < n_obs && obs_times[q1] <= b && (first || obs_times[q1] > a)) ++q1;
         e = launch_lds(s, a, b, q, q1);

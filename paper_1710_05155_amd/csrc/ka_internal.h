@@ -87,6 +87,10 @@ struct SweepLds {
   unsigned long long *obs_out;
   int R;
   uint32_t key0, key1;
+  // lattices: acceptance words of these sweeps generated beforehand (null: drawn in the loop),
+  // element ((plane * n_sweeps + s) * C + c) * acc_slots + j) * 1024 + thread
+  u64 *acc;
+  int acc_slots;
 };
 
 struct InitArgs {
@@ -124,6 +128,12 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
 hipError_t launch_init(const InitArgs &a, int R, int wpt, hipStream_t s);
 hipError_t launch_observe(const ObserveArgs &a, int wpt, hipStream_t s);
 size_t sweep_lds_bytes(int N, int wpt);
+// Edge slots per thread of the LDS lattice sweep (edges per class over its 1024 threads).
+int lds_lattice_slots(int d, int P);
+// Whether the LDS lattice sweep takes pre-generated acceptance words for this layout.
+bool lds_accept_supported(int d, int wpt);
+// Acceptance words of a.n_sweeps sweeps for the LDS lattice sweep, into a.acc.
+hipError_t launch_lds_accept(const SweepLds &a, int wpt, hipStream_t s);
 
 // Spatial four-point sums (ka_pairs.hip).
 constexpr int kMaxPairShells = 2049;   // r2_max <= 2048

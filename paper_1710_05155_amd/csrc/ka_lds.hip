@@ -91,7 +91,58 @@ __device__ void lds_observe_due(const SweepLds &a, const u64 *sn, const u64 *sf,
   }
 }
 
+// Element of the pre-generated acceptance words of sweep s (relative to t0), class c, slot j
+// for this thread.
+__device__ __forceinline__ int acc_element(const SweepLds &a, int plane, int s, int c, int j)
+{
+  return (((plane * a.n_sweeps + s) * a.C + c) * a.acc_slots + j) * kLdsBlock + (int)threadIdx.x;
+}
+
+// Acceptance words of sweeps t0 .. t0 + n_sweeps - 1 for k_sweep_lds_lattice: one workgroup per
+// (sweep, class) and plane, each thread drawing the words of its edge slots exactly as the sweep
+// loop maps them (the same sublattice, position and canonical edge id).  The words do not
+// depend on the state, so the whole device draws them ahead of the single-workgroup loop.
 template <int D, int WPT>
+__global__ __launch_bounds__(kLdsBlock) void k_lds_accept_lattice(SweepLds a)
+{
+  const int sc = (int)blockIdx.x;
+  const int s = sc / a.C, c = sc - s * a.C;
+  const int plane = (int)blockIdx.y;
+  const int mu = c >> 2;
+  constexpr int nsub = D == 2 ? 4 : 16;
+  const int per_class = nsub * a.g.P;
+  for (int j = 0; j < a.acc_slots; ++j) {
+    const int k = (int)threadIdx.x + j * kLdsBlock;
+    if (k >= per_class) break;
+    const int q = k / a.g.P;
+    const int sub = class_sublattice(D, mu, c & 3, q);
+    const Site si = decode(a.g, D, sub, k - q * a.g.P);
+    const uint32_t e = (uint32_t)canonical(a.g, D, si) * (uint32_t)D + (uint32_t)mu;
+    u64 r[WPT];
+    accept_words<WPT>(a.t0 + (uint32_t)s, (uint32_t)c, e, plane, a.key0, a.key1, a.noise, r);
+    Elem<WPT> v;
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) v.w[w] = r[w];
+    st<WPT>(a.acc, acc_element(a, plane, s, c, j), v);
+  }
+}
+
+// One lattice edge of the LDS sweep with its acceptance words given.
+template <int D, int MU, int WPT>
+__device__ __forceinline__ void lattice_edge_given(u64 *nb, u64 *fb, const LatticeGeom &g,
+                                                   const Site &si, const Elem<WPT> &rw, int m)
+{
+  constexpr int K = 2 * D - 1;
+  int i, j, ii[K], jj[K];
+  uint32_t e;
+  lattice_edge_indices<D, MU>(g, si, i, j, ii, jj, e);
+  edge_update_with<K, WPT>(nb, fb, i, j, ii, jj, m, [&](u64 (&r)[WPT]) {
+#pragma unroll
+    for (int w = 0; w < WPT; ++w) r[w] = rw.w[w];
+  });
+}
+
+template <int D, int WPT, bool GIVEN>
 __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int m)
 {
   extern __shared__ u64 lds[];
@@ -117,10 +168,29 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int
     slot_q[j] = q;
     slot_site[j] = decode(a.g, D, 0, k - q * a.g.P);   // idx = pos, residues 0
   }
+  // With pre-generated acceptance words, those of the next class are loaded while this
+  // class is processed (the loads stay in flight across the barrier).
+  Elem<WPT> rnext[kLdsSlots];
+  if constexpr (GIVEN) {
+#pragma unroll
+    for (int j = 0; j < kLdsSlots; ++j)
+      if (tid + j * kLdsBlock < per_class) rnext[j] = ld<WPT>(a.acc, acc_element(a, plane, 0, 0, j));
+  }
   for (int s = 0; s < a.n_sweeps; ++s) {
     const uint32_t t = a.t0 + (uint32_t)s;
     for (int c = 0; c < a.C; ++c) {
       const int mu = c >> 2;
+      Elem<WPT> rcur[kLdsSlots];
+      if constexpr (GIVEN) {
+        const int s2 = c + 1 < a.C ? s : s + 1;
+        const int c2 = c + 1 < a.C ? c + 1 : 0;
+#pragma unroll
+        for (int j = 0; j < kLdsSlots; ++j) {
+          rcur[j] = rnext[j];
+          if (s2 < a.n_sweeps && tid + j * kLdsBlock < per_class)
+            rnext[j] = ld<WPT>(a.acc, acc_element(a, plane, s2, c2, j));
+        }
+      }
 #pragma unroll
       for (int j = 0; j < kLdsSlots; ++j) {
         if (tid + j * kLdsBlock >= per_class) break;
@@ -130,6 +200,15 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int
         si.a[1] = (sub >> 2) & 3;
         si.a[2] = (sub >> 4) & 3;
         si.idx += sub * a.g.P;
+        if constexpr (GIVEN) {
+          if (mu == 0)
+            lattice_edge_given<D, 0, WPT>(sn, sf, a.g, si, rcur[j], m);
+          else if (mu == 1)
+            lattice_edge_given<D, 1, WPT>(sn, sf, a.g, si, rcur[j], m);
+          else if constexpr (D == 3)
+            lattice_edge_given<D, 2, WPT>(sn, sf, a.g, si, rcur[j], m);
+          continue;
+        }
         if (mu == 0)
           lattice_edge_at<D, 0, WPT>(sn, sf, a.g, si, plane, m, t, (uint32_t)c, a.key0, a.key1,
                                      a.noise);
@@ -183,6 +262,31 @@ hipError_t set_lds(Kern k, size_t bytes)
 
 size_t sweep_lds_bytes(int N, int wpt) { return (size_t)2 * (size_t)N * (size_t)wpt * 8u; }
 
+int lds_lattice_slots(int d, int P) { return ((d == 2 ? 4 : 16) * P + kLdsBlock - 1) / kLdsBlock; }
+
+// The sweep loop with given acceptance words keeps the next class's words in registers; with
+// 3D word pairs that does not fit the 128 registers a 1024-thread workgroup allows, so that
+// variant draws its words in the loop.
+bool lds_accept_supported(int d, int wpt) { return !(d == 3 && wpt == 2); }
+
+hipError_t launch_lds_accept(const SweepLds &a, int wpt, hipStream_t s)
+{
+  const int planes = (a.R / 64) / wpt;
+  if (!a.acc || a.n_sweeps < 1 || a.acc_slots < 1 || a.acc_slots > kLdsSlots ||
+      a.acc_slots != lds_lattice_slots(a.g.d, a.g.P) || !lds_accept_supported(a.g.d, wpt))
+    return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(a.n_sweeps * a.C), (unsigned)planes);
+  const dim3 block(kLdsBlock);
+  if (a.g.d == 2) {
+    if (wpt == 2) hipLaunchKernelGGL((k_lds_accept_lattice<2, 2>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_lds_accept_lattice<2, 1>), grid, block, 0, s, a);
+  } else {
+    if (wpt == 2) hipLaunchKernelGGL((k_lds_accept_lattice<3, 2>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_lds_accept_lattice<3, 1>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
 int max_lds_bytes()
 {
   int dev = 0, v = 0;
@@ -198,11 +302,11 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
   const dim3 grid((unsigned)planes);
   const dim3 block(kLdsBlock);
   hipError_t e = hipSuccess;
-#define KA_LDS_L(D, W)                                                            \
+#define KA_LDS_L(D, W, G)                                                         \
   do {                                                                            \
-    e = set_lds(k_sweep_lds_lattice<D, W>, lds_bytes);                            \
+    e = set_lds(k_sweep_lds_lattice<D, W, G>, lds_bytes);                         \
     if (e == hipSuccess)                                                          \
-      hipLaunchKernelGGL((k_sweep_lds_lattice<D, W>), grid, block, lds_bytes, s, a, m); \
+      hipLaunchKernelGGL((k_sweep_lds_lattice<D, W, G>), grid, block, lds_bytes, s, a, m); \
   } while (0)
 #define KA_LDS_G(Z, W)                                                            \
   do {                                                                            \
@@ -212,10 +316,18 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
   } while (0)
   if (lattice && (a.g.d == 2 ? 4 : 16) * a.g.P > kLdsSlots * kLdsBlock) return hipErrorInvalidValue;
   if (lattice) {
+    if (a.acc && !lds_accept_supported(a.g.d, wpt)) return hipErrorInvalidValue;
+    const bool g = a.acc != nullptr;
     if (a.g.d == 2) {
-      if (wpt == 2) KA_LDS_L(2, 2); else KA_LDS_L(2, 1);
+      if (wpt == 2) {
+        if (g) KA_LDS_L(2, 2, true); else KA_LDS_L(2, 2, false);
+      } else {
+        if (g) KA_LDS_L(2, 1, true); else KA_LDS_L(2, 1, false);
+      }
     } else {
-      if (wpt == 2) KA_LDS_L(3, 2); else KA_LDS_L(3, 1);
+      if (wpt == 2) KA_LDS_L(3, 2, false);
+      else if (g) KA_LDS_L(3, 1, true);
+      else KA_LDS_L(3, 1, false);
     }
   } else {
     switch (zdeg * 4 + wpt) {

@@ -80,6 +80,9 @@ struct ka_sim {
   int plane_streams = 0;          // KA_OPT_PLANE_STREAMS
   size_t lds_bytes = 0;
   bool lds_fits = false;
+  ka::u64 *lds_acc = nullptr;     // LDS lattice sweep: pre-generated acceptance words
+  int64_t lds_acc_sweeps = 0;     // sweeps lds_acc holds (0: words drawn in the loop)
+  bool lds_acc_tried = false;
   int64_t timing_every = 0;
   int64_t launches = 0;
   int64_t timed = 0;
