@@ -402,3 +402,38 @@ def test_valu_probe():
         ka.ka_probe_valu(2)
     with pytest.raises(ka.KaError):
         ka.ka_probe_valu(0, iters=0)
+
+
+@pytest.mark.parametrize("R", [64, 256])
+def test_lds_chunk_boundaries(oracle, R):
+    """The LDS-resident lattice sweep runs in chunks of sweeps whose acceptance words are
+    generated ahead (128 sweeps per chunk for one 2D L=64 plane, 32 for two), counted from
+    the time a call starts: sweeps and observations that start, end or sit exactly at chunk
+    boundaries match the oracle."""
+    g = ka.ka_graph_lattice(2, 64)
+    og = oracle.lattice(2, 64)
+    K = oracle.k_from_rho(og.N, 0.7)
+    chunk = 128 if R == 64 else 32
+    _say(f"LDS chunk boundaries R={R}")
+    sim = ka.ka_init_k(g, 2, K, 3, R)
+    ka.ka_set_option(sim, ka.KA_OPT_PATH, 2)
+    replicas = [0, R - 1]
+    orc = oracle.Sim(og, 2, K, 3, replicas)
+    ka.ka_sweep(sim, chunk - 1)
+    orc.sweep(chunk - 1)
+    # the run starts at t0 = chunk - 1, so its chunks end at t0 + chunk, t0 + 2 chunk, ...
+    times = [chunk, chunk, chunk + 1, 2 * chunk - 1, 2 * chunk, 3 * chunk - 1, 3 * chunk, 4 * chunk]
+    dens, ov, pers = ka.ka_run(sim, times)
+    for q, t in enumerate(times):
+        orc.sweep(t - orc.t)
+        od, oo, op = orc.observe()
+        for k, b in enumerate(replicas):
+            assert (dens[q, b], ov[q, b], pers[q, b]) == (od[k], oo[k], op[k]), (t, b)
+    ka.ka_sweep(sim, chunk + 3)
+    orc.sweep(chunk + 3)
+    n, n0, f, t = ka.ka_get_state(sim)
+    assert t == orc.t
+    for k, b in enumerate(replicas):
+        assert np.array_equal(((n[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.occ[k])
+        assert np.array_equal(((f[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.moved[k])
+    sim.free()
