@@ -150,8 +150,14 @@ bool observe_due(Job *j)
 void finish(ka_server *sv, std::unique_ptr<Job> j)
 {
   if (!j->done_ev) {
-    if (hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming) == hipSuccess)
-      (void)hipEventRecord(j->done_ev, sv->stream);
+    hipError_t e = hipEventCreateWithFlags(&j->done_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(j->done_ev, sv->stream);
+    if (e != hipSuccess) {
+      // no event to poll: wait here, so that retire() never reads counts still in flight
+      if (j->done_ev) (void)hipEventDestroy(j->done_ev);
+      j->done_ev = nullptr;
+      (void)hipStreamSynchronize(sv->stream);
+    }
   }
   sv->finishing.push_back(std::move(j));
 }
