@@ -130,3 +130,24 @@ def test_division_by_multiply_is_exact():
             for n in (k * Q - 1, k * Q, k * Q + 1, k * Q + Q - 1):
                 if 0 <= n < 2**31:
                     assert (2 * n * M) >> 64 == n // Q, (Q, n)
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """With no built library the binding raises; it has no other implementation to fall to."""
+    monkeypatch.setattr(ka, "LIB_PATH", str(tmp_path / "absent" / "libka.so"))
+    monkeypatch.setattr(ka, "_lib", None)
+    with pytest.raises(ka.KaError, match="not built"):
+        ka.ka_graph_lattice(2, 8)
+
+
+def test_product_never_imports_the_oracle():
+    """Only tests, the smoke check and the benchmark's CPU baseline may use oracle/: no source
+    of the package names it."""
+    pkg = os.path.join(ROOT, "paper_1710_05155_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for name in files:
+            if not name.endswith((".py", ".hip", ".cpp", ".h")):
+                continue
+            with open(os.path.join(dirpath, name)) as fh:
+                text = fh.read()
+            assert not re.search(r"\boracle\b|liboracle|ka_oracle", text), os.path.join(dirpath, name)
