@@ -499,6 +499,9 @@ void free_device(ka_sim *s)
   (void)hipFree(s->lds_acc);
   s->lds_acc = nullptr;
   s->lds_acc_sweeps = 0;
+  (void)hipFree(s->lds_snap);
+  s->lds_snap = nullptr;
+  s->lds_snap_rows = 0;
   s->n = s->n0 = s->f = nullptr;
 }
 
@@ -677,6 +680,10 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
 
 constexpr int64_t kLdsChunk = 20000;            // sweeps per LDS-resident launch
 constexpr size_t kLdsAccBudget = (size_t)8 << 20;  // bytes of pre-generated acceptance words
+// Observations of an LDS-resident launch are copied out as snapshots of n and f and counted
+// on the whole device after the launch, when its snapshots fit this many bytes; otherwise the
+// launch's one workgroup counts them in place.
+constexpr size_t kLdsSnapBudget = (size_t)4 << 20;
 
 // Sweeps per launch and buffer bytes of the pre-generated acceptance words of an LDS lattice
 // sweep (d, L, R); 0 sweeps if that layout draws its words in the loop.
@@ -738,10 +745,59 @@ hipError_t ensure_obs_buffers(ka_sim *s, size_t n_obs)
   return hipSuccess;
 }
 
-// LDS-resident launch covering sweeps [t_from, t_to) that also records observations
-// obs[q0..q1) (absolute times) into counts rows q0..q1.
-hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
+// Bytes of one snapshot row of the LDS-resident path: n and f of every plane.
+size_t lds_snap_row_bytes(int64_t N, int R) { return 2u * (size_t)N * (size_t)(R / 64) * 8u; }
+
+// Room for `rows` snapshot rows within kLdsSnapBudget; false if they do not fit it or the
+// allocation fails (the observations are then counted in the loop).  Called at the start of
+// ka_run, when no queued work uses the old buffer.
+bool ensure_lds_snap(ka_sim *s, size_t rows)
 {
+  const size_t row = lds_snap_row_bytes(s->N, s->R);
+  if (rows == 0 || rows * row > kLdsSnapBudget) return false;
+  if (rows <= s->lds_snap_rows) return true;
+  (void)hipFree(s->lds_snap);
+  s->lds_snap = nullptr;
+  s->lds_snap_rows = 0;
+  const size_t want = std::min(kLdsSnapBudget / row, std::max<size_t>(rows, 32));
+  if (dalloc(&s->lds_snap, want * row) != hipSuccess) {
+    (void)hipGetLastError();
+    s->lds_snap = nullptr;
+    return false;
+  }
+  s->lds_snap_rows = want;
+  return true;
+}
+
+// Count `rows` states into counts rows q0.. on the whole device: n and f of row r start at
+// n + r * stride and f + r * stride (stride 0: the same state for every row).
+hipError_t observe_rows(ka_sim *s, const ka::u64 *n, const ka::u64 *f, size_t stride, int q0, int rows)
+{
+  ka::ObserveArgs a{};
+  a.n0 = s->n0;
+  a.N = (int)s->N;
+  a.planes = s->planes;
+  a.R = s->R;
+  a.row_stride = stride;
+  hipError_t e = hipSuccess;
+  for (int r0 = 0; r0 < rows && e == hipSuccess; r0 += 65535) {   // grid z limit
+    a.n = n + (size_t)r0 * stride;
+    a.f = f + (size_t)r0 * stride;
+    a.out = s->counts + (size_t)(q0 + r0) * 3u * (size_t)s->R;
+    a.rows = std::min(rows - r0, 65535);
+    e = ka::launch_observe(a, s->wpt, s->stream);
+  }
+  return e;
+}
+
+// LDS-resident launch covering sweeps [t_from, t_to) that also records observations
+// obs[q0..q1) (absolute times) into counts rows q0..q1 (which start at zero): with `snap` as
+// snapshots counted by the observation kernel after the launch (lds_snap holds q1 - q0 rows),
+// otherwise counted in the loop.
+hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1, bool snap)
+{
+  if (q1 > q0 && t_to == t_from)   // no sweep: every observation is of the current state
+    return observe_rows(s, s->n, s->f, 0, q0, q1 - q0);
   ka::SweepLds a{};
   a.n = s->n;
   a.f = s->f;
@@ -769,7 +825,17 @@ hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1)
     hipError_t e = ka::launch_lds_accept(a, s->wpt, s->stream);
     if (e != hipSuccess) return e;
   }
-  return ka::launch_sweep_lds(a, s->lattice != 0, s->z, s->m, s->wpt, s->lds_bytes, s->stream);
+  const bool snapshots = snap && q1 > q0;
+  if (snapshots) {
+    if (!s->lds_snap || (size_t)(q1 - q0) > s->lds_snap_rows) return hipErrorInvalidValue;
+    a.snap = s->lds_snap;
+  }
+  hipError_t e = ka::launch_sweep_lds(a, s->lattice != 0, s->z, s->m, s->wpt, s->lds_bytes, s->stream);
+  if (e == hipSuccess && snapshots) {
+    const size_t row_words = (size_t)s->N * (size_t)s->W;
+    e = observe_rows(s, s->lds_snap, s->lds_snap + row_words, 2u * row_words, q0, q1 - q0);
+  }
+  return e;
 }
 
 hipError_t sweep_global(ka_sim *s, int64_t n)
@@ -798,18 +864,7 @@ hipError_t sweep_global(ka_sim *s, int64_t n)
   return e;
 }
 
-hipError_t observe_global(ka_sim *s, int row)
-{
-  ka::ObserveArgs a{};
-  a.n = s->n;
-  a.n0 = s->n0;
-  a.f = s->f;
-  a.N = (int)s->N;
-  a.planes = s->planes;
-  a.R = s->R;
-  a.out = s->counts + (size_t)row * 3u * (size_t)s->R;
-  return ka::launch_observe(a, s->wpt, s->stream);
-}
+hipError_t observe_global(ka_sim *s, int row) { return observe_rows(s, s->n, s->f, 0, row, 1); }
 
 // After a stream synchronisation: report a failure flagged by the initial-state kernels.
 int check_init_flag(ka_sim *s)
@@ -1015,13 +1070,14 @@ extern "C" int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_by
     if (n_replicas <= 0 || n_replicas % 64 != 0) return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
     *device_bytes = state_bytes(g->N, n_replicas) + graph_device_bytes(g) +
                     (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u;
-    if (g->lattice) {
+    const int wpt = ((n_replicas / 64) % 2 == 0) ? 2 : 1;
+    if (ka::sweep_lds_bytes((int)g->N, wpt) + 4096 <= (size_t)ka::max_lds_bytes()) {
       // an instance on the LDS-resident path adds its pre-generated acceptance words
-      const int wpt = ((n_replicas / 64) % 2 == 0) ? 2 : 1;
+      // (lattices) and its observation snapshots
       size_t acc = 0;
-      if (ka::sweep_lds_bytes((int)g->N, wpt) + 4096 <= (size_t)ka::max_lds_bytes())
-        (void)lds_acc_plan(g->d, g->L, n_replicas, &acc);
-      *device_bytes += acc;
+      if (g->lattice) (void)lds_acc_plan(g->d, g->L, n_replicas, &acc);
+      const size_t row = lds_snap_row_bytes(g->N, n_replicas);
+      *device_bytes += acc + (kLdsSnapBudget / row) * row;
     }
     return KA_OK;
   });
@@ -1172,7 +1228,7 @@ extern "C" int ka_sweep(ka_sim *s, int64_t n_sweeps)
       while (done < n_sweeps && e == hipSuccess) {
         const int64_t chunk = std::min(lds_chunk(s), n_sweeps - done);
         e = ensure_obs_buffers(s, 1);
-        if (e == hipSuccess) e = launch_lds(s, s->t + done, s->t + done + chunk, 0, 0);
+        if (e == hipSuccess) e = launch_lds(s, s->t + done, s->t + done + chunk, 0, 0, false);
         done += chunk;
       }
     } else {
@@ -1207,19 +1263,27 @@ extern "C" int ka_run(ka_sim *s, const int64_t *obs_times, int n_obs, int64_t *d
       e = hipMemcpyAsync(s->obs_d, obs_times, (size_t)n_obs * sizeof(int64_t), hipMemcpyHostToDevice, s->stream);
       // chunks [a, b) of at most lds_chunk sweeps; observation q goes to the first chunk
       // that can record it (times in [a, b] for the first chunk, (a, b] afterwards)
+      struct Chunk {
+        int64_t a, b;
+        int q0, q1;
+      };
+      std::vector<Chunk> plan;
       int q = 0;
       int64_t a = s->t;
-      bool first = true;
       const int64_t chunk = lds_chunk(s);
-      while (e == hipSuccess && q < n_obs) {
+      size_t most = 0;   // observations of the fullest chunk that sweeps
+      while (q < n_obs) {
         const int64_t b = std::min(a + chunk, obs_times[n_obs - 1]);
         int q1 = q;
-        while (q1 < n_obs && obs_times[q1] <= b && (first || obs_times[q1] > a)) ++q1;
-        e = launch_lds(s, a, b, q, q1);
+        while (q1 < n_obs && obs_times[q1] <= b && (plan.empty() || obs_times[q1] > a)) ++q1;
+        plan.push_back({a, b, q, q1});
+        if (b > a) most = std::max(most, (size_t)(q1 - q));
         q = q1;
         a = b;
-        first = false;
       }
+      const bool snap = most > 0 && ensure_lds_snap(s, most);
+      for (size_t k = 0; k < plan.size() && e == hipSuccess; ++k)
+        e = launch_lds(s, plan[k].a, plan[k].b, plan[k].q0, plan[k].q1, snap);
     } else {
       for (int q = 0; q < n_obs && e == hipSuccess; ++q) {
         const int64_t n = obs_times[q] - s->t;

@@ -91,6 +91,10 @@ struct SweepLds {
   // element ((plane * n_sweeps + s) * C + c) * acc_slots + j) * 1024 + thread
   u64 *acc;
   int acc_slots;
+  // observations as state snapshots (null: counted in the loop): row q holds n of every plane,
+  // then f of every plane, each in the global layout ([planes][N][wpt]); counted afterwards by
+  // the observation kernel
+  u64 *snap;
 };
 
 struct InitArgs {
@@ -117,7 +121,9 @@ struct ObserveArgs {
   int N;
   int planes;
   int R;
-  unsigned long long *out;   // [3][R]: density, overlap, persistence
+  unsigned long long *out;   // [rows][3][R]: density, overlap, persistence (added to)
+  int rows;                  // states counted by one launch (at least 1)
+  size_t row_stride;         // elements from one row's n (and f) to the next; 0: one state
 };
 
 // Launchers (ka_kernels.hip).  Return hipSuccess or the launch error.

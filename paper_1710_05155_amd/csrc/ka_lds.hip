@@ -81,12 +81,29 @@ __device__ void lds_store(const SweepLds &a, const u64 *sn, const u64 *sf, int p
   }
 }
 
+// Copy of the plane's n and f into snapshot row `row` (layout in SweepLds::snap), for the
+// observation kernel to count after this launch on the whole device.
+template <int WPT>
+__device__ void lds_snapshot(const SweepLds &a, const u64 *sn, const u64 *sf, int plane, int row)
+{
+  const int words = a.N * WPT;                                // one plane
+  const size_t row_words = (size_t)(a.R / 64) * (size_t)a.N;  // every plane, n or f
+  u64 *dn = a.snap + (size_t)row * 2u * row_words + (size_t)plane * (size_t)words;
+  u64 *df = dn + row_words;
+  for (int q = (int)threadIdx.x; q < words; q += (int)blockDim.x) {
+    dn[q] = sn[q];
+    df[q] = sf[q];
+  }
+  __syncthreads();   // the next pass rewrites sn and sf
+}
+
 template <int WPT>
 __device__ void lds_observe_due(const SweepLds &a, const u64 *sn, const u64 *sf, int plane,
                                 int &qo, int64_t t_now, unsigned *cnt)
 {
   while (qo < a.n_obs && a.obs_times[qo] == t_now) {
-    lds_observe<WPT>(a, sn, sf, plane, qo, cnt);
+    if (a.snap) lds_snapshot<WPT>(a, sn, sf, plane, qo);
+    else lds_observe<WPT>(a, sn, sf, plane, qo, cnt);
     ++qo;
   }
 }

@@ -83,6 +83,8 @@ struct ka_sim {
   ka::u64 *lds_acc = nullptr;     // LDS lattice sweep: pre-generated acceptance words
   int64_t lds_acc_sweeps = 0;     // sweeps lds_acc holds (0: words drawn in the loop)
   bool lds_acc_tried = false;
+  ka::u64 *lds_snap = nullptr;    // LDS sweep: snapshots of n and f taken at observation times
+  size_t lds_snap_rows = 0;       // snapshot rows lds_snap holds
   int64_t timing_every = 0;
   int64_t launches = 0;
   int64_t timed = 0;

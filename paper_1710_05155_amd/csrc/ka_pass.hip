@@ -59,14 +59,18 @@ __global__ __launch_bounds__(BLOCK) void k_pass_graph(PassGraph a, int m)
                      a.c, a.key0, a.key1, a.noise);
 }
 
+// One launch counts a.rows states (blockIdx.z): the sim's own state, or snapshots taken by the
+// LDS-resident sweep loop.
 template <int WPT>
 __global__ __launch_bounds__(kObsBlock) void k_observe(ObserveArgs a)
 {
   const int plane = blockIdx.y;
+  const int row = blockIdx.z;
   const int lane = (int)__lane_id();
   const int wave = (int)(blockIdx.x * (kObsBlock / 64) + threadIdx.x / 64);
   const int nwaves = (int)(gridDim.x * (kObsBlock / 64));
   const size_t off = (size_t)plane * (size_t)a.N * WPT;
+  const size_t soff = off + (size_t)row * a.row_stride;
   unsigned acc[3][WPT];
 #pragma unroll
   for (int o = 0; o < 3; ++o)
@@ -76,9 +80,9 @@ __global__ __launch_bounds__(kObsBlock) void k_observe(ObserveArgs a)
     const int idx = base + lane;
     Elem<WPT> x, x0, xf;
     if (idx < a.N) {
-      x = ld<WPT>(a.n + off, idx);
+      x = ld<WPT>(a.n + soff, idx);
       x0 = ld<WPT>(a.n0 + off, idx);
-      xf = ld<WPT>(a.f + off, idx);
+      xf = ld<WPT>(a.f + soff, idx);
     } else {
 #pragma unroll
       for (int w = 0; w < WPT; ++w) x.w[w] = x0.w[w] = xf.w[w] = 0;
@@ -90,12 +94,13 @@ __global__ __launch_bounds__(kObsBlock) void k_observe(ObserveArgs a)
       vertical_count(x0.w[w] & ~xf.w[w], acc[2][w]);
     }
   }
+  unsigned long long *out = a.out + (size_t)row * 3u * (size_t)a.R;
 #pragma unroll
   for (int o = 0; o < 3; ++o)
 #pragma unroll
     for (int w = 0; w < WPT; ++w)
       if (acc[o][w])
-        atomicAdd(&a.out[(size_t)o * a.R + (size_t)(plane * WPT + w) * 64 + lane],
+        atomicAdd(&out[(size_t)o * a.R + (size_t)(plane * WPT + w) * 64 + lane],
                   (unsigned long long)acc[o][w]);
 }
 
@@ -343,9 +348,10 @@ hipError_t launch_init(const InitArgs &a, int R, int wpt, hipStream_t s)
 
 hipError_t launch_observe(const ObserveArgs &a, int wpt, hipStream_t s)
 {
+  if (a.rows < 1 || a.rows > 65535) return hipErrorInvalidValue;
   int bx = (a.N + kObsBlock - 1) / kObsBlock;
   if (bx > 512) bx = 512;
-  const dim3 grid((unsigned)bx, (unsigned)a.planes);
+  const dim3 grid((unsigned)bx, (unsigned)a.planes, (unsigned)a.rows);
   if (wpt == 2)
     hipLaunchKernelGGL((k_observe<2>), grid, dim3(kObsBlock), 0, s, a);
   else

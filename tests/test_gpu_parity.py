@@ -437,3 +437,25 @@ def test_lds_chunk_boundaries(oracle, R):
         assert np.array_equal(((n[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.occ[k])
         assert np.array_equal(((f[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.moved[k])
     sim.free()
+
+
+def test_lds_observations_snapshot_and_in_place(oracle):
+    """The LDS-resident path takes observations as snapshots counted on the whole device when
+    they fit its snapshot budget (4 MiB: 64 rows of 64 KiB for 2D L=64 x 64), and counts them
+    in place on its one workgroup otherwise.  Both give the oracle's counts."""
+    g = ka.ka_graph_lattice(2, 64)
+    og = oracle.lattice(2, 64)
+    K = oracle.k_from_rho(og.N, 0.7)
+    replicas = list(range(64))
+    for times in (list(range(0, 60)) + [70, 90], list(range(0, 101))):
+        _say(f"LDS observations: {len(times)} in one chunk")
+        sim = ka.ka_init_k(g, 2, K, 8, 64)
+        ka.ka_set_option(sim, ka.KA_OPT_PATH, 2)
+        dens, ov, pers = ka.ka_run(sim, times)
+        orc = oracle.Sim(og, 2, K, 8, replicas)
+        for q, t in enumerate(times):
+            orc.sweep(t - orc.t)
+            od, oo, op = orc.observe()
+            assert np.array_equal(dens[q], od) and np.array_equal(ov[q], oo) and np.array_equal(pers[q], op), t
+        _state_equal(sim, orc)
+        sim.free()
