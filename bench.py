@@ -567,6 +567,12 @@ def main():
                               "valu_busy_pct": valu, "kernel": kernel, "avg_launch_us": avg_s * 1e6,
                               "bytes_per_launch": B, "launches": pass_launches,
                               "sampled_launch_us": pass_ms_total / pass_timed * 1000.0 if pass_timed else None}
+        if w["kind"] == "lattice":
+            # For comparison only: the floor of a schedule that would read and write each n word
+            # once per sweep (all classes fused), 16 B per 64 site-replica attempts.
+            floor_gbs = (attempts / (sweep_ms / 1000.0)) * 0.25 / 1e9
+            result["roofline"]["fused_floor"] = {"bytes_per_attempt": 0.25, "achieved": floor_gbs,
+                                                 "frac": floor_gbs / HBM_PEAK_GBS}
     if args.calibrate_alu:
         cal = {}
         for kind, name in ((0, "v_xor_b32"), (1, "v_mad_u64_u32")):
