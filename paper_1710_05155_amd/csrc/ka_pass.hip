@@ -123,9 +123,30 @@ constexpr int kDig = 12;
 constexpr int kBins = 1 << kDig;
 constexpr int kCap = 2048;
 
+constexpr int kBinsPerThread = kBins / kSelBlock;
+
 __device__ __forceinline__ bool key_matches(u64 u, u64 prefix, int pbits)
 {
   return pbits == 0 || (u >> (64 - pbits)) == prefix;
+}
+
+// Exclusive prefix sum of v over the kSelBlock threads of the block (every thread calls it;
+// tmp holds one value per wave).  Counts stay below 2^32: at most N <= 2^31 keys.
+__device__ __forceinline__ unsigned block_exclusive_scan(unsigned v, unsigned *tmp)
+{
+  const int lane = (int)__lane_id();
+  const int wave = (int)threadIdx.x / 64;
+  unsigned x = v;   // inclusive scan within the wave
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const unsigned y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63) tmp[wave] = x;
+  __syncthreads();
+  unsigned off = 0;
+  for (int w = 0; w < wave; ++w) off += tmp[w];
+  return off + x - v;
 }
 
 __global__ __launch_bounds__(kSelBlock) void k_init_select(InitArgs a)
@@ -138,6 +159,9 @@ __global__ __launch_bounds__(kSelBlock) void k_init_select(InitArgs a)
   __shared__ long long need[2];
   __shared__ int done[2];
   __shared__ int ncand[2];
+  __shared__ int sel_beta[2];
+  __shared__ unsigned sel_cum[2];
+  __shared__ unsigned scan_tmp[kSelBlock / 64];
   const int hp = blockIdx.x;
   const int tid = (int)threadIdx.x;
   if (a.K == 0) {
@@ -171,20 +195,47 @@ __global__ __launch_bounds__(kSelBlock) void k_init_select(InitArgs a)
         atomicAdd(&hist[h][digit], 1u);
       }
     }
+    // The bin holding the need-th key: the one bin b with E[b] < need <= E[b] + hist[b],
+    // E the exclusive prefix sum of the histogram, found by a block-wide scan (thread t owns
+    // bins kBinsPerThread * t ...).  The scan's own barrier orders these initial values
+    // before the one thread that finds the bin writes it.
+    if (tid < 2) {
+      sel_beta[tid] = -1;
+      sel_cum[tid] = 0;
+    }
+    __syncthreads();   // the histogram is complete
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if (done[h]) continue;   // block-uniform
+      unsigned c[kBinsPerThread];
+      unsigned sum = 0;
+#pragma unroll
+      for (int q = 0; q < kBinsPerThread; ++q) {
+        c[q] = hist[h][kBinsPerThread * tid + q];
+        sum += c[q];
+      }
+      const unsigned before = block_exclusive_scan(sum, scan_tmp);
+      unsigned e = before;
+#pragma unroll
+      for (int q = 0; q < kBinsPerThread; ++q) {
+        if ((long long)e < need[h] && need[h] <= (long long)e + (long long)c[q]) {
+          sel_beta[h] = kBinsPerThread * tid + q;
+          sel_cum[h] = e;
+        }
+        e += c[q];
+      }
+      __syncthreads();   // scan_tmp is reused by the next h
+    }
     __syncthreads();
     if (tid < 2 && !done[tid]) {
       const int h = tid;
       const int pb = pbits[h];
       const int dig = (64 - pb) < kDig ? (64 - pb) : kDig;
-      long long cum = 0;
-      int beta = 0;
-      for (beta = 0; beta < (1 << dig); ++beta) {
-        const long long c = hist[h][beta];
-        if (cum + c >= need[h]) break;
-        cum += c;
-      }
-      if (beta >= (1 << dig)) {  // unreachable: need <= keys under the prefix
+      int beta = sel_beta[h];
+      long long cum = sel_cum[h];
+      if (beta < 0 || beta >= (1 << dig)) {  // unreachable: need <= keys under the prefix
         beta = (1 << dig) - 1;
+        cum = 0;
         atomicOr(a.err, 2);
       }
       need[h] -= cum;
