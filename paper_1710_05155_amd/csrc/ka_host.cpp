@@ -692,9 +692,9 @@ int64_t lds_acc_plan(int d, int L, int R, size_t *bytes)
   const int wpt = ((R / 64) % 2 == 0) ? 2 : 1;
   const int planes = (R / 64) / wpt;
   if (bytes) *bytes = 0;
-  if (!ka::lds_accept_supported(d, wpt)) return 0;
   const int Q = L / 4;
   const int P = d == 2 ? Q * Q : Q * Q * Q;
+  if (!ka::lds_accept_supported(d, wpt, ka::lds_lattice_slots(d, P))) return 0;
   const size_t per_sweep = (size_t)planes * (size_t)(4 * d) * (size_t)ka::lds_lattice_slots(d, P) * 1024u *
                            (size_t)wpt * 8u;
   const int64_t sweeps = std::max<int64_t>(1, std::min<int64_t>(kLdsChunk, (int64_t)(kLdsAccBudget / per_sweep)));

@@ -137,7 +137,7 @@ size_t sweep_lds_bytes(int N, int wpt);
 // Edge slots per thread of the LDS lattice sweep (edges per class over its 1024 threads).
 int lds_lattice_slots(int d, int P);
 // Whether the LDS lattice sweep takes pre-generated acceptance words for this layout.
-bool lds_accept_supported(int d, int wpt);
+bool lds_accept_supported(int d, int wpt, int slots);
 // Acceptance words of a.n_sweeps sweeps for the LDS lattice sweep, into a.acc.
 hipError_t launch_lds_accept(const SweepLds &a, int wpt, hipStream_t s);
 

@@ -159,7 +159,9 @@ __device__ __forceinline__ void lattice_edge_given(u64 *nb, u64 *fb, const Latti
   });
 }
 
-template <int D, int WPT, bool GIVEN>
+// SLOTS: edge slots per thread the kernel is compiled for (the class size over 1024, rounded
+// up, must not exceed it).
+template <int D, int WPT, bool GIVEN, int SLOTS = kLdsSlots>
 __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int m)
 {
   extern __shared__ u64 lds[];
@@ -176,10 +178,10 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int
   // the class, the q-th lower-endpoint sublattice at position pos.  The divisions and the
   // block coordinates of pos are done once, here; per class only the residues change.
   const int tid = (int)threadIdx.x;
-  int slot_q[kLdsSlots];
-  Site slot_site[kLdsSlots];
+  int slot_q[SLOTS];
+  Site slot_site[SLOTS];
 #pragma unroll
-  for (int j = 0; j < kLdsSlots; ++j) {
+  for (int j = 0; j < SLOTS; ++j) {
     const int k = tid + j * kLdsBlock;
     const int q = k / a.g.P;
     slot_q[j] = q;
@@ -187,29 +189,29 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int
   }
   // With pre-generated acceptance words, those of the next class are loaded while this
   // class is processed (the loads stay in flight across the barrier).
-  Elem<WPT> rnext[kLdsSlots];
+  Elem<WPT> rnext[SLOTS];
   if constexpr (GIVEN) {
 #pragma unroll
-    for (int j = 0; j < kLdsSlots; ++j)
+    for (int j = 0; j < SLOTS; ++j)
       if (tid + j * kLdsBlock < per_class) rnext[j] = ld<WPT>(a.acc, acc_element(a, plane, 0, 0, j));
   }
   for (int s = 0; s < a.n_sweeps; ++s) {
     const uint32_t t = a.t0 + (uint32_t)s;
     for (int c = 0; c < a.C; ++c) {
       const int mu = c >> 2;
-      Elem<WPT> rcur[kLdsSlots];
+      Elem<WPT> rcur[SLOTS];
       if constexpr (GIVEN) {
         const int s2 = c + 1 < a.C ? s : s + 1;
         const int c2 = c + 1 < a.C ? c + 1 : 0;
 #pragma unroll
-        for (int j = 0; j < kLdsSlots; ++j) {
+        for (int j = 0; j < SLOTS; ++j) {
           rcur[j] = rnext[j];
           if (s2 < a.n_sweeps && tid + j * kLdsBlock < per_class)
             rnext[j] = ld<WPT>(a.acc, acc_element(a, plane, s2, c2, j));
         }
       }
 #pragma unroll
-      for (int j = 0; j < kLdsSlots; ++j) {
+      for (int j = 0; j < SLOTS; ++j) {
         if (tid + j * kLdsBlock >= per_class) break;
         const int sub = class_sublattice(D, mu, c & 3, slot_q[j]);
         Site si = slot_site[j];
@@ -281,16 +283,17 @@ size_t sweep_lds_bytes(int N, int wpt) { return (size_t)2 * (size_t)N * (size_t)
 
 int lds_lattice_slots(int d, int P) { return ((d == 2 ? 4 : 16) * P + kLdsBlock - 1) / kLdsBlock; }
 
-// The sweep loop with given acceptance words keeps the next class's words in registers; with
-// 3D word pairs that does not fit the 128 registers a 1024-thread workgroup allows, so that
-// variant draws its words in the loop.
-bool lds_accept_supported(int d, int wpt) { return !(d == 3 && wpt == 2); }
+// The sweep loop with given acceptance words keeps the next class's words in registers.  For
+// 3D word pairs it is compiled for one edge slot per thread, the most a 3D plane of word pairs
+// that fits in LDS needs (L = 16: 1024 edges per class); three slots would not fit the 128
+// registers a 1024-thread workgroup allows.
+bool lds_accept_supported(int d, int wpt, int slots) { return !(d == 3 && wpt == 2 && slots > 1); }
 
 hipError_t launch_lds_accept(const SweepLds &a, int wpt, hipStream_t s)
 {
   const int planes = (a.R / 64) / wpt;
   if (!a.acc || a.n_sweeps < 1 || a.acc_slots < 1 || a.acc_slots > kLdsSlots ||
-      a.acc_slots != lds_lattice_slots(a.g.d, a.g.P) || !lds_accept_supported(a.g.d, wpt))
+      a.acc_slots != lds_lattice_slots(a.g.d, a.g.P) || !lds_accept_supported(a.g.d, wpt, a.acc_slots))
     return hipErrorInvalidValue;
   const dim3 grid((unsigned)(a.n_sweeps * a.C), (unsigned)planes);
   const dim3 block(kLdsBlock);
@@ -333,7 +336,7 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
   } while (0)
   if (lattice && (a.g.d == 2 ? 4 : 16) * a.g.P > kLdsSlots * kLdsBlock) return hipErrorInvalidValue;
   if (lattice) {
-    if (a.acc && !lds_accept_supported(a.g.d, wpt)) return hipErrorInvalidValue;
+    if (a.acc && !lds_accept_supported(a.g.d, wpt, lds_lattice_slots(a.g.d, a.g.P))) return hipErrorInvalidValue;
     const bool g = a.acc != nullptr;
     if (a.g.d == 2) {
       if (wpt == 2) {
@@ -342,8 +345,15 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
         if (g) KA_LDS_L(2, 1, true); else KA_LDS_L(2, 1, false);
       }
     } else {
-      if (wpt == 2) KA_LDS_L(3, 2, false);
-      else if (g) KA_LDS_L(3, 1, true);
+      if (wpt == 2) {
+        if (g) {
+          e = set_lds(k_sweep_lds_lattice<3, 2, true, 1>, lds_bytes);
+          if (e == hipSuccess)
+            hipLaunchKernelGGL((k_sweep_lds_lattice<3, 2, true, 1>), grid, block, lds_bytes, s, a, m);
+        } else {
+          KA_LDS_L(3, 2, false);
+        }
+      } else if (g) KA_LDS_L(3, 1, true);
       else KA_LDS_L(3, 1, false);
     }
   } else {
