@@ -101,10 +101,10 @@ int ka_graph_export(const ka_graph *g, int32_t *adj, int32_t *edge_u, int32_t *e
 void ka_graph_free(ka_graph *g);
 
 /* Device bytes a sim of this graph with n_replicas replicas allocates (serving admission).
- * For an instance whose word plane fits in LDS this includes, for lattices, the buffer of
- * acceptance words that its LDS-resident sweeps generate ahead (at most 8 MiB, allocated on
- * the first such sweep), and the state snapshots its ka_run observations are counted from (at
- * most 4 MiB, allocated by the first ka_run that takes them). */
+ * For an instance whose word plane fits in LDS this includes the buffer of acceptance words
+ * that its LDS-resident sweeps generate ahead (at most 8 MiB, allocated on the first such
+ * sweep), and the state snapshots its ka_run observations are counted from (at most 4 MiB,
+ * allocated by the first ka_run that takes them). */
 int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_bytes);
 
 /* Create a simulation of n_replicas (a positive multiple of 64) independent replicas on the

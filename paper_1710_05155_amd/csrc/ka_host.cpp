@@ -702,16 +702,39 @@ int64_t lds_acc_plan(int d, int L, int R, size_t *bytes)
   return sweeps;
 }
 
-// Sweeps per LDS-resident launch of this sim; for a lattice whose layout takes pre-generated
-// acceptance words, allocates their buffer on first use (if that fails, the words are drawn in
-// the loop and launches cover up to kLdsChunk sweeps).
+// The same for the LDS graph sweep over E class-sorted edges of degree z whose largest class
+// has max_class edges; 0 sweeps if a class has more edges per thread than the sweep prefetches
+// or the layout draws its words in the loop.
+int64_t lds_acc_plan_graph(int64_t E, int max_class, int z, int R, size_t *bytes)
+{
+  if (bytes) *bytes = 0;
+  const int wpt = ((R / 64) % 2 == 0) ? 2 : 1;
+  if (E < 1 || ka::lds_graph_slots(max_class) > ka::kLdsGraphAcceptSlots || !ka::lds_graph_accept_supported(z, wpt))
+    return 0;
+  const size_t per_sweep = (size_t)E * (size_t)(R / 64) * 8u;   // every plane's words
+  const int64_t sweeps = std::max<int64_t>(1, std::min<int64_t>(kLdsChunk, (int64_t)(kLdsAccBudget / per_sweep)));
+  if (bytes) *bytes = (size_t)sweeps * per_sweep;
+  return sweeps;
+}
+
+int max_class_edges(const std::vector<int> &class_start)
+{
+  int most = 0;
+  for (size_t c = 0; c + 1 < class_start.size(); ++c) most = std::max(most, class_start[c + 1] - class_start[c]);
+  return most;
+}
+
+// Sweeps per LDS-resident launch of this sim; when its layout takes pre-generated acceptance
+// words, allocates their buffer on first use (if that fails, the words are drawn in the loop
+// and launches cover up to kLdsChunk sweeps).
 int64_t lds_chunk(ka_sim *s)
 {
-  if (!s->lattice) return kLdsChunk;
   if (!s->lds_acc_tried) {
     s->lds_acc_tried = true;
     size_t bytes = 0;
-    const int64_t sweeps = lds_acc_plan(s->geom.d, s->geom.L, s->R, &bytes);
+    const int64_t sweeps = s->lattice ? lds_acc_plan(s->geom.d, s->geom.L, s->R, &bytes)
+                                      : lds_acc_plan_graph((int64_t)s->edges_total,
+                                                           max_class_edges(s->plan->class_start), s->z, s->R, &bytes);
     if (sweeps > 0 && dalloc(&s->lds_acc, bytes) == hipSuccess) {
       s->lds_acc_sweeps = sweeps;
     } else {
@@ -818,11 +841,12 @@ hipError_t launch_lds(ka_sim *s, int64_t t_from, int64_t t_to, int q0, int q1, b
   a.key0 = (uint32_t)s->seed;
   a.key1 = (uint32_t)(s->seed >> 32);
   a.noise = s->noise;
-  if (s->lattice && s->lds_acc && a.n_sweeps > 0) {
+  if (s->lds_acc && a.n_sweeps > 0) {
     if (a.n_sweeps > s->lds_acc_sweeps) return hipErrorInvalidValue;
     a.acc = s->lds_acc;
-    a.acc_slots = ka::lds_lattice_slots(s->geom.d, s->geom.P);
-    hipError_t e = ka::launch_lds_accept(a, s->wpt, s->stream);
+    a.acc_slots = s->lattice ? ka::lds_lattice_slots(s->geom.d, s->geom.P)
+                             : ka::lds_graph_slots(max_class_edges(s->plan->class_start));
+    hipError_t e = ka::launch_lds_accept(a, s->lattice != 0, s->wpt, s->stream);
     if (e != hipSuccess) return e;
   }
   const bool snapshots = snap && q1 > q0;
@@ -1014,7 +1038,7 @@ std::shared_ptr<const GraphPlan> graph_plan(const ka_graph *g)
     rec.resize((size_t)E);
     for (int64_t q = 0; q < E; ++q)
       rec[(size_t)fill[(size_t)g->ecls[q]]++] =
-          make_int4(label[(size_t)g->eu[q]], label[(size_t)g->ev[q]], (int)q, 0);
+          make_int4(label[(size_t)g->eu[q]], label[(size_t)g->ev[q]], (int)q, (int)g->ecls[q]);
     // Owner of an edge: its endpoints' part when they share one (key: the smaller endpoint
     // number); else, alternating with the canonical id, one endpoint's part (key: that
     // endpoint's number).  Inside a class, edges go by owner part, then by key.
@@ -1072,10 +1096,17 @@ extern "C" int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_by
                     (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u;
     const int wpt = ((n_replicas / 64) % 2 == 0) ? 2 : 1;
     if (ka::sweep_lds_bytes((int)g->N, wpt) + 4096 <= (size_t)ka::max_lds_bytes()) {
-      // an instance on the LDS-resident path adds its pre-generated acceptance words
-      // (lattices) and its observation snapshots
+      // an instance on the LDS-resident path adds its pre-generated acceptance words and its
+      // observation snapshots
       size_t acc = 0;
-      if (g->lattice) (void)lds_acc_plan(g->d, g->L, n_replicas, &acc);
+      if (g->lattice) {
+        (void)lds_acc_plan(g->d, g->L, n_replicas, &acc);
+      } else {
+        std::vector<int> cs((size_t)g->C + 1, 0);
+        for (int32_t c : g->ecls) cs[(size_t)c + 1] += 1;
+        for (size_t c = 1; c < cs.size(); ++c) cs[c] += cs[c - 1];
+        (void)lds_acc_plan_graph((int64_t)g->ecls.size(), max_class_edges(cs), g->z, n_replicas, &acc);
+      }
       const size_t row = lds_snap_row_bytes(g->N, n_replicas);
       *device_bytes += acc + (kLdsSnapBudget / row) * row;
     }

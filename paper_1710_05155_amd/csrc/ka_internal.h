@@ -52,7 +52,7 @@ struct PassLattice {
 struct PassGraph {
   u64 *n;
   u64 *f;
-  const int4 *edges;         // all edges sorted by class: (u, v, e, 0)
+  const int4 *edges;         // all edges sorted by class: (u, v, e, class)
   const int32_t *nbr;        // [2(z-1)][E] neighbour lists of the records above
   size_t stride;             // E
   int first;                 // first edge of the class
@@ -72,7 +72,7 @@ struct SweepLds {
   // lattice
   LatticeGeom g;
   // graph
-  const int4 *edges;         // all edges sorted by class
+  const int4 *edges;         // all edges sorted by class: (u, v, e, class)
   const int32_t *nbr;        // [2(z-1)][E]
   size_t stride;             // E
   const int *class_start;    // [C+1]
@@ -87,8 +87,10 @@ struct SweepLds {
   unsigned long long *obs_out;
   int R;
   uint32_t key0, key1;
-  // lattices: acceptance words of these sweeps generated beforehand (null: drawn in the loop),
-  // element ((plane * n_sweeps + s) * C + c) * acc_slots + j) * 1024 + thread
+  // acceptance words of these sweeps generated beforehand (null: drawn in the loop).
+  // Lattices: element (((plane * n_sweeps + s) * C + c) * acc_slots + j) * 1024 + thread.
+  // Graphs: element (plane * n_sweeps + s) * E + k for class-sorted edge k (E = stride), and
+  // acc_slots is the most edges any class gives one of the 1024 threads.
   u64 *acc;
   int acc_slots;
   // observations as state snapshots (null: counted in the loop): row q holds n of every plane,
@@ -138,8 +140,13 @@ size_t sweep_lds_bytes(int N, int wpt);
 int lds_lattice_slots(int d, int P);
 // Whether the LDS lattice sweep takes pre-generated acceptance words for this layout.
 bool lds_accept_supported(int d, int wpt, int slots);
-// Acceptance words of a.n_sweeps sweeps for the LDS lattice sweep, into a.acc.
-hipError_t launch_lds_accept(const SweepLds &a, int wpt, hipStream_t s);
+// Edge slots per thread of the LDS graph sweep for its largest class, and the most it takes
+// pre-generated acceptance words for.
+int lds_graph_slots(int max_class_edges);
+constexpr int kLdsGraphAcceptSlots = 3;
+bool lds_graph_accept_supported(int z, int wpt);
+// Acceptance words of a.n_sweeps sweeps for the LDS lattice or graph sweep, into a.acc.
+hipError_t launch_lds_accept(const SweepLds &a, bool lattice, int wpt, hipStream_t s);
 
 // Spatial four-point sums (ka_pairs.hip).
 constexpr int kMaxPairShells = 2049;   // r2_max <= 2048
@@ -171,7 +178,7 @@ constexpr int kBatchMaxMembers = 1024;
 struct BatchMember {
   u64 *n;
   u64 *f;
-  const int4 *edges;           // graphs: class-sorted (u, v, e, 0)
+  const int4 *edges;           // graphs: class-sorted (u, v, e, class)
   const int32_t *nbr;          // graphs: [2(z-1)][E] neighbour lists
   long long stride;            // graphs: E
   const int *class_start;      // graphs: [C+1]

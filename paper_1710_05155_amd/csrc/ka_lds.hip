@@ -159,6 +159,27 @@ __device__ __forceinline__ void lattice_edge_given(u64 *nb, u64 *fb, const Latti
   });
 }
 
+// Acceptance words of sweeps t0 .. t0 + n_sweeps - 1 for k_sweep_lds_graph: blockIdx.x runs
+// over (sweep, block of 1024 class-sorted edges), blockIdx.y over planes; each thread draws
+// the words of one edge from its record (canonical id e, class c), as the sweep loop would.
+template <int WPT>
+__global__ __launch_bounds__(kLdsBlock) void k_lds_accept_graph(SweepLds a)
+{
+  const int E = (int)a.stride;
+  const int nblk = (E + kLdsBlock - 1) / kLdsBlock;
+  const int s = (int)blockIdx.x / nblk;
+  const int k = ((int)blockIdx.x - s * nblk) * kLdsBlock + (int)threadIdx.x;
+  const int plane = (int)blockIdx.y;
+  if (k >= E) return;
+  const int4 rec = a.edges[k];
+  u64 r[WPT];
+  accept_words<WPT>(a.t0 + (uint32_t)s, (uint32_t)rec.w, (uint32_t)rec.z, plane, a.key0, a.key1, a.noise, r);
+  Elem<WPT> rw;
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) rw.w[w] = r[w];
+  st<WPT>(a.acc, (plane * a.n_sweeps + s) * E + k, rw);
+}
+
 // SLOTS: edge slots per thread the kernel is compiled for (the class size over 1024, rounded
 // up, must not exceed it).
 template <int D, int WPT, bool GIVEN, int SLOTS = kLdsSlots>
@@ -245,7 +266,9 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_lattice(SweepLds a, int
   lds_store<WPT>(a, sn, sf, plane);
 }
 
-template <int Z, int WPT>
+// GIVEN: the acceptance words come from a.acc (every class has at most kLdsGraphAcceptSlots
+// edges per thread), those of the next class loaded while this class is processed.
+template <int Z, int WPT, bool GIVEN>
 __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_graph(SweepLds a, int m)
 {
   extern __shared__ u64 lds[];
@@ -253,16 +276,65 @@ __global__ __launch_bounds__(kLdsBlock) void k_sweep_lds_graph(SweepLds a, int m
   u64 *sn = lds;
   u64 *sf = lds + (size_t)a.N * WPT;
   const int plane = blockIdx.x;
+  const int tid = (int)threadIdx.x;
+  const int E = (int)a.stride;
   lds_load<WPT>(a, sn, sf, plane);
   int qo = 0;
   lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)a.t0, cnt);
+  constexpr int S = kLdsGraphAcceptSlots;
+  Elem<WPT> rnext[S];
+  if constexpr (GIVEN) {
+    const int b0 = a.class_start[0], b1 = a.class_start[1];
+#pragma unroll
+    for (int j = 0; j < S; ++j)
+      if (b0 + tid + j * kLdsBlock < b1) rnext[j] = ld<WPT>(a.acc, plane * a.n_sweeps * E + b0 + tid + j * kLdsBlock);
+  }
   for (int s = 0; s < a.n_sweeps; ++s) {
     const uint32_t t = a.t0 + (uint32_t)s;
     for (int c = 0; c < a.C; ++c) {
       const int b0 = a.class_start[c], b1 = a.class_start[c + 1];
-      for (int k = b0 + (int)threadIdx.x; k < b1; k += (int)blockDim.x)
-        graph_edge<Z, WPT>(sn, sf, a.edges, a.nbr, a.stride, k, plane, m, t, (uint32_t)c, a.key0,
-                           a.key1, a.noise);
+      if constexpr (GIVEN) {
+        // This class's records and neighbour lists are loaded before the next class's words:
+        // vector loads complete in order, so waiting for the records leaves the words in
+        // flight while this class is processed.
+        constexpr int K = Z - 1;
+        int4 rec[S];
+        int iu[S][K], iv[S][K];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          const int k = b0 + tid + j * kLdsBlock;
+          if (k < b1) {
+            rec[j] = a.edges[k];
+#pragma unroll
+            for (int q = 0; q < K; ++q) {
+              iu[j][q] = a.nbr[(size_t)q * a.stride + (size_t)k];
+              iv[j][q] = a.nbr[(size_t)(K + q) * a.stride + (size_t)k];
+            }
+          }
+        }
+        Elem<WPT> rcur[S];
+        const int s2 = c + 1 < a.C ? s : s + 1;
+        const int c2 = c + 1 < a.C ? c + 1 : 0;
+        const int n0 = a.class_start[c2], n1 = a.class_start[c2 + 1];
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          rcur[j] = rnext[j];
+          const int k2 = n0 + tid + j * kLdsBlock;
+          if (s2 < a.n_sweeps && k2 < n1) rnext[j] = ld<WPT>(a.acc, (plane * a.n_sweeps + s2) * E + k2);
+        }
+#pragma unroll
+        for (int j = 0; j < S; ++j) {
+          if (b0 + tid + j * kLdsBlock >= b1) break;
+          edge_update_with<K, WPT>(sn, sf, rec[j].x, rec[j].y, iu[j], iv[j], m, [&](u64 (&r)[WPT]) {
+#pragma unroll
+            for (int w = 0; w < WPT; ++w) r[w] = rcur[j].w[w];
+          });
+        }
+      } else {
+        for (int k = b0 + tid; k < b1; k += (int)blockDim.x)
+          graph_edge<Z, WPT>(sn, sf, a.edges, a.nbr, a.stride, k, plane, m, t, (uint32_t)c, a.key0,
+                             a.key1, a.noise);
+      }
       __syncthreads();
     }
     lds_observe_due<WPT>(a, sn, sf, plane, qo, (int64_t)t + 1, cnt);
@@ -289,9 +361,27 @@ int lds_lattice_slots(int d, int P) { return ((d == 2 ? 4 : 16) * P + kLdsBlock 
 // registers a 1024-thread workgroup allows.
 bool lds_accept_supported(int d, int wpt, int slots) { return !(d == 3 && wpt == 2 && slots > 1); }
 
-hipError_t launch_lds_accept(const SweepLds &a, int wpt, hipStream_t s)
+int lds_graph_slots(int max_class_edges) { return (max_class_edges + kLdsBlock - 1) / kLdsBlock; }
+
+// With given words the graph sweep holds each slot's record, neighbour ids and words in
+// registers; for z = 6 with word pairs that exceeds the 128 a 1024-thread workgroup allows, so
+// that layout draws its words in the loop.
+bool lds_graph_accept_supported(int z, int wpt) { return !(z == 6 && wpt == 2); }
+
+hipError_t launch_lds_accept(const SweepLds &a, bool lattice, int wpt, hipStream_t s)
 {
   const int planes = (a.R / 64) / wpt;
+  if (!lattice) {
+    const int E = (int)a.stride;
+    const int nblk = (E + kLdsBlock - 1) / kLdsBlock;
+    if (!a.acc || a.n_sweeps < 1 || E < 1 || a.acc_slots < 1 || a.acc_slots > kLdsGraphAcceptSlots ||
+        (long long)a.n_sweeps * nblk > 0x7FFFFFFFLL)
+      return hipErrorInvalidValue;
+    const dim3 grid((unsigned)(a.n_sweeps * nblk), (unsigned)planes);
+    if (wpt == 2) hipLaunchKernelGGL((k_lds_accept_graph<2>), grid, dim3(kLdsBlock), 0, s, a);
+    else hipLaunchKernelGGL((k_lds_accept_graph<1>), grid, dim3(kLdsBlock), 0, s, a);
+    return hipGetLastError();
+  }
   if (!a.acc || a.n_sweeps < 1 || a.acc_slots < 1 || a.acc_slots > kLdsSlots ||
       a.acc_slots != lds_lattice_slots(a.g.d, a.g.P) || !lds_accept_supported(a.g.d, wpt, a.acc_slots))
     return hipErrorInvalidValue;
@@ -328,11 +418,15 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
     if (e == hipSuccess)                                                          \
       hipLaunchKernelGGL((k_sweep_lds_lattice<D, W, G>), grid, block, lds_bytes, s, a, m); \
   } while (0)
+#define KA_LDS_G1(Z, W, G)                                                        \
+  do {                                                                            \
+    e = set_lds(k_sweep_lds_graph<Z, W, G>, lds_bytes);                           \
+    if (e == hipSuccess)                                                          \
+      hipLaunchKernelGGL((k_sweep_lds_graph<Z, W, G>), grid, block, lds_bytes, s, a, m); \
+  } while (0)
 #define KA_LDS_G(Z, W)                                                            \
   do {                                                                            \
-    e = set_lds(k_sweep_lds_graph<Z, W>, lds_bytes);                              \
-    if (e == hipSuccess)                                                          \
-      hipLaunchKernelGGL((k_sweep_lds_graph<Z, W>), grid, block, lds_bytes, s, a, m); \
+    if (a.acc) KA_LDS_G1(Z, W, true); else KA_LDS_G1(Z, W, false);                 \
   } while (0)
   if (lattice && (a.g.d == 2 ? 4 : 16) * a.g.P > kLdsSlots * kLdsBlock) return hipErrorInvalidValue;
   if (lattice) {
@@ -357,6 +451,8 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
       else KA_LDS_L(3, 1, false);
     }
   } else {
+    if (a.acc && (a.acc_slots < 1 || a.acc_slots > kLdsGraphAcceptSlots || !lds_graph_accept_supported(zdeg, wpt)))
+      return hipErrorInvalidValue;
     switch (zdeg * 4 + wpt) {
       case 3 * 4 + 1: KA_LDS_G(3, 1); break;
       case 3 * 4 + 2: KA_LDS_G(3, 2); break;
@@ -365,12 +461,13 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
       case 5 * 4 + 1: KA_LDS_G(5, 1); break;
       case 5 * 4 + 2: KA_LDS_G(5, 2); break;
       case 6 * 4 + 1: KA_LDS_G(6, 1); break;
-      case 6 * 4 + 2: KA_LDS_G(6, 2); break;
+      case 6 * 4 + 2: KA_LDS_G1(6, 2, false); break;   // see lds_graph_accept_supported
       default: return hipErrorInvalidValue;
     }
   }
 #undef KA_LDS_L
 #undef KA_LDS_G
+#undef KA_LDS_G1
   if (e != hipSuccess) return e;
   return hipGetLastError();
 }

@@ -20,7 +20,7 @@ struct GraphPlan {
   std::vector<int32_t> label;     // device index of canonical vertex i
   std::vector<int32_t> site_of;   // canonical vertex of device index
   std::vector<int> class_start;   // [C+1]
-  std::vector<int4> rec;          // class-sorted (u, v, e, 0)
+  std::vector<int4> rec;          // class-sorted (u, v, e, class)
   std::vector<int32_t> nbr;       // [2(z-1)][E] neighbour lists of rec
 };
 
