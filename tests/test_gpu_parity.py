@@ -459,3 +459,38 @@ def test_lds_observations_snapshot_and_in_place(oracle):
             assert np.array_equal(dens[q], od) and np.array_equal(ov[q], oo) and np.array_equal(pers[q], op), t
         _state_equal(sim, orc)
         sim.free()
+
+
+@pytest.mark.parametrize("z,R", [(4, 64), (3, 128)])
+def test_lds_graph_chunk_boundaries(oracle, z, R):
+    """The LDS-resident graph sweep with acceptance words generated ahead per chunk of sweeps
+    (8 MiB of words: 128 sweeps for N=4096, z=4 x 64 replicas; 85 for z=3 x 128): sweeps and
+    observations that start, end or sit on chunk boundaries match the oracle."""
+    N = 4096
+    g = ka.ka_graph_rrg(N, z, 23)
+    oadj, _ = oracle.rrg_adjacency(N, z, 23)
+    og = oracle.graph_from_adjacency(oadj)
+    K = oracle.k_from_rho(N, 0.6)
+    chunk = min(20000, (8 << 20) // (g.E * (R // 64) * 8))
+    _say(f"LDS graph chunk boundaries z={z} R={R} chunk={chunk}")
+    sim = ka.ka_init_k(g, 2, K, 5, R)
+    ka.ka_set_option(sim, ka.KA_OPT_PATH, 2)
+    replicas = [0, R - 1]
+    orc = oracle.Sim(og, 2, K, 5, replicas)
+    ka.ka_sweep(sim, chunk - 1)
+    orc.sweep(chunk - 1)
+    times = [chunk, chunk + 1, 2 * chunk - 1, 2 * chunk, 2 * chunk + 3]
+    dens, ov, pers = ka.ka_run(sim, times)
+    for q, t in enumerate(times):
+        orc.sweep(t - orc.t)
+        od, oo, op = orc.observe()
+        for k, b in enumerate(replicas):
+            assert (dens[q, b], ov[q, b], pers[q, b]) == (od[k], oo[k], op[k]), (t, b)
+    ka.ka_sweep(sim, chunk + 2)
+    orc.sweep(chunk + 2)
+    n, n0, f, t = ka.ka_get_state(sim)
+    assert t == orc.t
+    for k, b in enumerate(replicas):
+        assert np.array_equal(((n[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.occ[k])
+        assert np.array_equal(((f[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.moved[k])
+    sim.free()
