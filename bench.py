@@ -52,14 +52,17 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def class_pass_bytes(w, N, W):
-    """Algorithmic HBM bytes of one global class pass over all words (per-pass model):
-    every site's words are read once as endpoint or neighbour (8 B), the endpoints (half of
-    the sites) are written (8 B) and their moved-ever words read (8 B).  A moved-ever word
-    is written only when it gains a bit (at most 64 times per word over a whole run), which
-    the model leaves out."""
+def class_pass_bytes(w, N, W, with_moved_ever=False):
+    """Algorithmic HBM bytes of one global class pass over all words, per-pass model: every
+    site's words are read once as endpoint or neighbour (8 B) and the endpoints (half of the
+    sites) are written (8 B): 12 B per site-word.  with_moved_ever adds a read of every
+    endpoint's moved-ever word (8 B per endpoint, 16 B per site-word in all); the kernel reads
+    it only where an exchange happens, and writes it only where it gains a bit."""
     if w["kind"] == "lattice":
-        return N * W * 8 + (N // 2) * W * 8 + (N // 2) * W * 8
+        b = N * W * 8 + (N // 2) * W * 8
+        if with_moved_ever:
+            b += (N // 2) * W * 8
+        return b
     return None
 
 
@@ -473,7 +476,7 @@ def main():
             run_events.append(evs)
         K = sim.K
         assert (dens == K).all(), "particle number not conserved"
-        C, chi4, P = ka.derived_observables(N, K, ov, pers)
+        C, chi4, P = ka.ka_derived(N, K, ov, pers)
         stats = ka.ka_timing(sim)
         path = ka.ka_sim_path(sim)
         sim.free()
@@ -541,32 +544,59 @@ def main():
         "observe_ms_per_step": obs_ms,
     }
     B = class_pass_bytes(w, N, W)
+    B16 = class_pass_bytes(w, N, W, with_moved_ever=True)
     kernel = "k_pass_lattice"
     if w["kind"] != "lattice":
         adj, eu, ev, ec = ka.ka_graph_export(g)
         B = graph_bytes_model(adj, eu, ev, ec, g.C, g.z, W) / g.C
+        B16 = None
         kernel = "k_pass_graph"
     if path == 1 and pass_launches > 0 and B:
         # B is one class step over all word planes; a lattice sim with two or more planes
         # launches one kernel per plane and class step (on two streams, overlapping), so the
         # bytes of one launch are the step's bytes over the launches per step
         class_steps = sweeps * g.C * args.steps
-        B = B * class_steps / pass_launches
+        per_launch = class_steps / pass_launches
+        B = B * per_launch
         avg_s = sweep_ms / pass_launches / 1000.0
         achieved = B / avg_s / 1e9
         csrc = os.path.join(ROOT, "paper_1710_05155_amd", "csrc")
-        traffic = None
-        valu = None
-        if args.workload == "cubic128" and R == 256 and not args.plane_streams:
+        traffic = valu = trace_us = None
+        cfile = None
+        counters = {"cubic128": "k_pass_lattice_cubic128.counters.txt",
+                    "cubic256": "k_pass_lattice_cubic256.counters.txt",
+                    "rrg20": "k_pass_graph_rrg20.counters.txt"}.get(args.workload)
+        expected_R = {"cubic128": 256, "cubic256": 256, "rrg20": 64}.get(args.workload)
+        if counters and R == expected_R and not args.plane_streams and sweeps == WORKLOADS[args.workload]["sweeps"]:
             srcs = [os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")]
-            cfile = os.path.join(ROOT, "profiles", "k_pass_lattice_cubic128.counters.txt")
+            cfile = os.path.join(ROOT, "profiles", counters)
             traffic = measured_traffic(srcs, cfile)
             valu = measured_traffic(srcs, cfile, key="valu_busy_pct")
-        result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                              "valu_busy_pct": valu, "kernel": kernel, "avg_launch_us": avg_s * 1e6,
-                              "bytes_per_launch": B, "launches": pass_launches,
-                              "sampled_launch_us": pass_ms_total / pass_timed * 1000.0 if pass_timed else None}
+            trace_us = measured_traffic(srcs, cfile, key="trace_avg_launch_us")
+        result["roofline"] = {
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_source": (f"profiles/{os.path.basename(cfile)}: rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE "
+                               "runs, scaled by a plain copy's counts; null when the kernel sources no "
+                               "longer hash to the ones counted") if traffic is not None else None,
+            "valu_busy_pct": valu, "kernel": kernel, "avg_launch_us": avg_s * 1e6,
+            "bytes_per_launch": B,
+            "byte_model": ("12 B per site-word: every site's words read once, the endpoints' written"
+                           if w["kind"] == "lattice" else
+                           "per class: touched sites x 8 B per word + records + neighbour lists + endpoint "
+                           "writes and moved-ever reads"),
+            "launches": pass_launches,
+            "sampled_launch_us": pass_ms_total / pass_timed * 1000.0 if pass_timed else None}
+        if trace_us:
+            # the same figure from the committed rocprofv3 kernel trace of this command
+            result["roofline"]["trace_avg_launch_us"] = trace_us
+            result["roofline"]["trace_frac"] = B / (trace_us / 1e6) / 1e9 / HBM_PEAK_GBS
+        if B16:
+            b16 = B16 * per_launch
+            result["roofline"]["with_moved_ever_reads"] = {
+                "bytes_per_launch": b16, "achieved": b16 / avg_s / 1e9,
+                "frac": b16 / avg_s / 1e9 / HBM_PEAK_GBS,
+                "model": "16 B per site-word: also a moved-ever read at every endpoint"}
         if w["kind"] == "lattice":
             # For comparison only: the floor of a schedule that would read and write each n word
             # once per sweep (all classes fused), 16 B per 64 site-replica attempts.

@@ -101,10 +101,12 @@ int ka_graph_export(const ka_graph *g, int32_t *adj, int32_t *edge_u, int32_t *e
 void ka_graph_free(ka_graph *g);
 
 /* Device bytes a sim of this graph with n_replicas replicas allocates (serving admission).
+ * No passage of the paper applies: this is library bookkeeping.
  * For an instance whose word plane fits in LDS this includes the buffer of acceptance words
  * that its LDS-resident sweeps generate ahead (at most 8 MiB, allocated on the first such
- * sweep), and the state snapshots its ka_run observations are counted from (at most 4 MiB,
- * allocated by the first ka_run that takes them). */
+ * sweep; a layout whose words for a single sweep would exceed 8 MiB draws them in the loop
+ * instead), and the state snapshots its ka_run observations are counted from (at most
+ * 4 MiB, allocated by the first ka_run that takes them). */
 int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_bytes);
 
 /* Create a simulation of n_replicas (a positive multiple of 64) independent replicas on the
@@ -122,7 +124,14 @@ int ka_init(const ka_graph *g, int m, double rho, uint64_t seed, int n_replicas,
 int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int n_replicas,
               void *hip_stream, ka_sim **out);
 
-/* Enqueue n_sweeps sweeps (t -> t + n_sweeps) on the sim's stream; does not synchronise. */
+/* Enqueue n_sweeps sweeps (t -> t + n_sweeps) on the sim's stream; does not synchronise.
+ * One sweep applies the exchange of Sec. 2.1 rules (a)-(c) to every edge once per replica,
+ * class by class as described at the top of this file; for all 64 replicas of a word at
+ * once it is the bitwise update of Sec. 3.2 (thresholds "at most m occupied neighbours
+ * other than the partner" on both ends, then the exchange of the two occupations where
+ * they differ), masked by the acceptance bits.  The moved-ever mask f gains the bits of
+ * both endpoints wherever the exchange happens.  KA_EINVAL if n_sweeps < 0, KA_ESTATE if t
+ * would reach 2^32 or the sim is a batch member. */
 int ka_sweep(ka_sim *s, int64_t n_sweeps);
 
 /* Per-replica counts at the current t (Sec. 2.2 overlap q_i(t) = n_i(t) n_i(0), summed
@@ -133,16 +142,20 @@ int ka_sweep(ka_sim *s, int64_t n_sweeps);
 int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
                int64_t *persistence);
 
-/* Spatial four-point sums at the current t on a lattice (Sec. 2.2 g4 and chi4 = sum_r g4;
- * Sec. 3.3 Phi(r, t) as the popcount of the AND of n_i(t), n_i(0), n_j(t), n_j(0)).  With
- * q_i^b = n_i^b(t) n_i^b(0), for every shell r2 = |delta|^2 <= r2_max of displacements delta
- * of the torus (each displacement once, components in the minimum image |c| <= L/2):
- *   S2[r2]    = sum_i sum_{|delta|^2 = r2} sum_b q_i^b q_{i+delta}^b            (= Phi)
- *   S11[r2]   = sum_i sum_{|delta|^2 = r2} (sum_b q_i^b) (sum_b q_{i+delta}^b)
- *   count[r2] = number of displacements in the shell.
+/* Spatial four-point sums at the current t (Sec. 2.2 g4 and chi4 = sum_r g4; Sec. 3.3
+ * Phi(r, t) as the popcount of the AND of n_i(t), n_i(0), n_j(t), n_j(0)), with
+ * q_i^b = n_i^b(t) n_i^b(0), over ordered site pairs (i, j) grouped in shells r2:
+ *   S2[r2]    = sum over pairs in the shell of sum_b q_i^b q_j^b                 (= Phi)
+ *   S11[r2]   = sum over pairs in the shell of (sum_b q_i^b) (sum_b q_j^b)
+ *   count[r2] = number of partners j of one site i in the shell.
+ * Lattices: j = i + delta for every displacement delta of the torus once (components in the
+ * minimum image |c| <= L/2), shell r2 = |delta|^2.  Other graphs (random regular, layered,
+ * any adjacency): the distance convention of Sec. 3.3 for graphs without a geometry, 0 for
+ * j = i and 1 for every j != i, so shell 0 holds the pairs (i, i) (count 1) and shell 1 all
+ * others (count N - 1); shells 2.. are 0.
  * Arrays of r2_max + 1 values (any may be NULL); r2_max <= 2048; up to 1024 replicas.
- * g4(r) = (S2/R - S11/R^2) / (N rho^2 (1-rho)^2) then sums to chi4 over all shells.
- * KA_EINVAL for general graphs.  Synchronises. */
+ * g4(r) = (S2/R - S11/R^2) / (N rho^2 (1-rho)^2) (ka_g4) then sums to chi4 over all shells.
+ * KA_EINVAL if a sum would not fit int64.  Synchronises. */
 int ka_observe_pairs(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *count);
 
 /* Run to each of the n_obs non-decreasing absolute sweep indices obs_times[q] (each >= the
@@ -152,8 +165,10 @@ int ka_observe_pairs(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *
 int ka_run(ka_sim *s, const int64_t *obs_times, int n_obs, int64_t *density,
            int64_t *overlap, int64_t *persistence);
 
-/* Copy the state out / in, canonical layout [W][N] each (any output may be NULL).
- * ka_set_state requires f to be consistent with the dynamics only for the meaning of
+/* Copy the state out / in, canonical layout [W][N] each (any output may be NULL).  No
+ * passage of the paper applies: this is checkpoint/resume of (n, n(0), f, t); because the
+ * random counters hold the absolute sweep t, a run resumed from a copy equals the unbroken
+ * run.  ka_set_state requires f to be consistent with the dynamics only for the meaning of
  * persistence; it is not checked.  Both synchronise the stream. */
 int ka_get_state(ka_sim *s, uint64_t *n, uint64_t *n0, uint64_t *f, int64_t *t);
 int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, const uint64_t *f,
@@ -323,6 +338,34 @@ void ka_server_free(ka_server *sv);
 /* ------------------------------------------------------------------------------------ */
 int ka_probe_valu(int kind, int iters, int blocks, void *hip_stream, double *instr_per_s,
                   double *lane_ops_per_s);
+
+/* ------------------------------------------------------------------------------------ */
+/* Host-side quantities derived from the counts (no device work; callable without a GPU). */
+/* ------------------------------------------------------------------------------------ */
+
+/* Particle number of density rho on N sites (Sec. 3.1: the configurations at fixed density
+ * rho): K = floor(rho*N + 1/2) in IEEE double, as ka_init uses.  KA_EINVAL if rho is outside
+ * [0, 1] or N < 1. */
+int ka_particles(int64_t N, double rho, int64_t *K);
+
+/* Replica averages of per-replica counts (Sec. 2.2), one value per row of the int64
+ * [n_rows][n_replicas] arrays overlap and persistence (as ka_run returns them), with
+ * r = K/N:
+ *   q_b  = (overlap_b / N - r^2) / (r (1 - r))          (the overlap normalised so q(0) = 1)
+ *   C    = mean_b q_b,   chi4 = N (mean_b q_b^2 - (mean_b q_b)^2)   (population variance)
+ *   P    = mean_b persistence_b / K.
+ * C and chi4 are NaN when K is 0 or N, P when K is 0.  Outputs double [n_rows] (any may be
+ * NULL; persistence may be NULL when P is).  KA_EINVAL on bad sizes. */
+int ka_derived(int64_t N, int64_t K, int n_replicas, int n_rows, const int64_t *overlap,
+               const int64_t *persistence, double *C, double *chi4, double *P);
+
+/* g4 per shell from the sums of ka_observe_pairs (Sec. 2.2): the replica covariance of the
+ * q fields summed over the shell's pairs, normalised by N r^2 (1-r)^2 with r = K/N (the
+ * normalisation under which the shells sum to chi4 of ka_derived):
+ *   g4[k] = (S2[k] / R - S11[k] / R^2) / (N r^2 (1 - r)^2),   R = n_replicas.
+ * NaN when K is 0 or N.  KA_EINVAL on bad sizes. */
+int ka_g4(int64_t N, int64_t K, int n_replicas, int n_shells, const int64_t *S2,
+          const int64_t *S11, double *g4);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char *ka_last_error(void);

@@ -389,6 +389,52 @@ def pair_sums(occ: np.ndarray, occ0: np.ndarray, d: int, L: int, r2_max: int):
     return S2, S11, count
 
 
+def graph_distance_tree(i: int, j: int) -> int:
+    """Distance on a graph without a geometry (Sec. 3.3): 0 for i = j, 1 otherwise."""
+    return 0 if i == j else 1
+
+
+def pair_sums_graph_bruteforce(occ: np.ndarray, occ0: np.ndarray, r2_max: int):
+    """S2, S11, count of Sec. 2.2 / Sec. 3.3 on a graph without a geometry by an explicit
+    loop over every ordered site pair (i, j), shell graph_distance_tree(i, j).  Tiny N only."""
+    R, N = occ.shape
+    q = occ.astype(np.int64) * occ0.astype(np.int64)
+    S2 = np.zeros(r2_max + 1, dtype=np.int64)
+    S11 = np.zeros(r2_max + 1, dtype=np.int64)
+    count = np.zeros(r2_max + 1, dtype=np.int64)
+    for i in range(N):
+        for j in range(N):
+            r = graph_distance_tree(i, j)
+            if r > r2_max:
+                continue
+            S2[r] += int((q[:, i] * q[:, j]).sum())
+            S11[r] += int(q[:, i].sum()) * int(q[:, j].sum())
+            if i == 0:
+                count[r] += 1
+    return S2, S11, count
+
+
+def pair_sums_graph(occ: np.ndarray, occ0: np.ndarray, r2_max: int):
+    """The same sums for any N: shell 0 is the pairs (i, i), shell 1 every ordered pair with
+    i != j, whose sums are the sums over all ordered pairs less the diagonal,
+    sum_{i != j} a_i b_j = (sum_i a_i)(sum_j b_j) - sum_i a_i b_i."""
+    R, N = occ.shape
+    q = occ.astype(np.int64) * occ0.astype(np.int64)     # (R, N)
+    Q = q.sum(axis=0)                                      # per site, summed over replicas
+    O = q.sum(axis=1)                                      # per replica, summed over sites
+    S2 = np.zeros(r2_max + 1, dtype=np.int64)
+    S11 = np.zeros(r2_max + 1, dtype=np.int64)
+    count = np.zeros(r2_max + 1, dtype=np.int64)
+    S2[0] = int((q * q).sum())
+    S11[0] = int((Q * Q).sum())
+    count[0] = 1
+    if r2_max >= 1:
+        S2[1] = int((O.astype(object) ** 2).sum()) - int((q * q).sum())
+        S11[1] = int(Q.sum()) ** 2 - int((Q * Q).sum())
+        count[1] = N - 1
+    return S2, S11, count
+
+
 def g4_from_pairs(N: int, K: int, R: int, S2, S11):
     """g4(r) = sum over pairs at r of the replica covariance of q_i, q_j, divided by
     N rho^2 (1-rho)^2 (the normalisation under which sum_r g4 = chi4 of Sec. 2.2)."""

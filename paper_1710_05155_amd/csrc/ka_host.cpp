@@ -697,6 +697,7 @@ int64_t lds_acc_plan(int d, int L, int R, size_t *bytes)
   if (!ka::lds_accept_supported(d, wpt, ka::lds_lattice_slots(d, P))) return 0;
   const size_t per_sweep = (size_t)planes * (size_t)(4 * d) * (size_t)ka::lds_lattice_slots(d, P) * 1024u *
                            (size_t)wpt * 8u;
+  if (per_sweep > kLdsAccBudget) return 0;   // drawn in the loop: the buffer stays within budget
   const int64_t sweeps = std::max<int64_t>(1, std::min<int64_t>(kLdsChunk, (int64_t)(kLdsAccBudget / per_sweep)));
   if (bytes) *bytes = (size_t)sweeps * per_sweep;
   return sweeps;
@@ -712,6 +713,7 @@ int64_t lds_acc_plan_graph(int64_t E, int max_class, int z, int R, size_t *bytes
   if (E < 1 || ka::lds_graph_slots(max_class) > ka::kLdsGraphAcceptSlots || !ka::lds_graph_accept_supported(z, wpt))
     return 0;
   const size_t per_sweep = (size_t)E * (size_t)(R / 64) * 8u;   // every plane's words
+  if (per_sweep > kLdsAccBudget) return 0;
   const int64_t sweeps = std::max<int64_t>(1, std::min<int64_t>(kLdsChunk, (int64_t)(kLdsAccBudget / per_sweep)));
   if (bytes) *bytes = (size_t)sweeps * per_sweep;
   return sweeps;
@@ -1394,15 +1396,67 @@ int ka_sim_take_own_stream(ka_sim *s, bool wait)
   return KA_OK;
 }
 
+namespace {
+
+// Four-point sums on a graph without a geometry (Sec. 3.3: distance 0 for i = j and 1 for
+// i != j).  With Q_i = sum_b q_i^b and O_b = sum_i q_i^b (the overlap count of replica b):
+//   shell 0: S2 = sum_i sum_b q_i^b = sum_b O_b,   S11 = sum_i Q_i^2,          count 1;
+//   shell 1: S2 = sum_b (O_b^2 - O_b),            S11 = (sum_i Q_i)^2 - sum_i Q_i^2, count N-1.
+int pair_sums_graph(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *count)
+{
+  std::vector<int64_t> ov((size_t)s->R);
+  int rc = ka_observe(s, nullptr, nullptr, ov.data(), nullptr);
+  if (rc) return rc;
+  DeviceGuard dg(s->device);
+  unsigned long long *d_out = nullptr;
+  unsigned long long host[2] = {0, 0};
+  hipError_t e = dalloc(&d_out, 2 * sizeof(unsigned long long));
+  if (e == hipSuccess) e = hipMemsetAsync(d_out, 0, 2 * sizeof(unsigned long long), s->stream);
+  if (e == hipSuccess) {
+    ka::PairGraphArgs a{};
+    a.n = s->n;
+    a.n0 = s->n0;
+    a.N = (int)s->N;
+    a.planes = s->planes;
+    a.out = d_out;
+    e = ka::launch_pairs_graph(a, s->wpt, s->stream);
+  }
+  if (e == hipSuccess) e = hipMemcpyAsync(host, d_out, sizeof(host), hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  (void)hipFree(d_out);
+  if (e != hipSuccess) return hip_fail(e, "ka_observe_pairs");
+  __int128 sum_o = 0, sum_o2 = 0;
+  for (int64_t o : ov) {
+    sum_o += o;
+    sum_o2 += (__int128)o * o;
+  }
+  const __int128 sq = (__int128)host[0];
+  const __int128 sq2 = (__int128)host[1];
+  if (sq != sum_o) return fail(KA_EDEVICE, "pair sums: per-site and per-replica overlap totals differ");
+  const __int128 lim = (__int128)INT64_MAX;
+  const __int128 s2_1 = sum_o2 - sum_o, s11_1 = sq * sq - sq2;
+  if (s2_1 > lim || s11_1 > lim) return fail(KA_EINVAL, "pair sums exceed int64 (N x n_replicas too large)");
+  for (int q = 0; q <= r2_max; ++q) {
+    const int64_t v2 = q == 0 ? (int64_t)sum_o : q == 1 ? (int64_t)s2_1 : 0;
+    const int64_t v11 = q == 0 ? (int64_t)sq2 : q == 1 ? (int64_t)s11_1 : 0;
+    if (S2) S2[q] = v2;
+    if (S11) S11[q] = v11;
+    if (count) count[q] = q == 0 ? 1 : q == 1 ? s->N - 1 : 0;
+  }
+  return KA_OK;
+}
+
+}  // namespace
+
 extern "C" int ka_observe_pairs(ka_sim *s, int r2_max, int64_t *S2, int64_t *S11, int64_t *count)
 {
   return ka_guard([&]() -> int {
     int rc = check_sim(s);
     if (rc) return rc;
-    if (!s->lattice) return fail(KA_EINVAL, "spatial pair sums need a lattice");
     if (r2_max < 0 || r2_max > ka::kMaxPairShells - 1)
       return fail(KA_EINVAL, "r2_max must be in [0, %d]", ka::kMaxPairShells - 1);
     if (s->W > 16) return fail(KA_EINVAL, "spatial pair sums support up to 1024 replicas");
+    if (!s->lattice) return pair_sums_graph(s, r2_max, S2, S11, count);
     const int d = s->geom.d, L = s->geom.L;
     // every displacement of the torus once, components in the minimum image (|c| <= L/2)
     std::vector<int4> disp;
@@ -1601,6 +1655,68 @@ extern "C" void ka_free(ka_sim *s)
     delete s;
   } catch (...) {
   }
+}
+
+// ------------------------------------------------------------------------------------
+// Host-side quantities derived from the counts (Sec. 2.2, Sec. 3.1).
+// ------------------------------------------------------------------------------------
+extern "C" int ka_particles(int64_t N, double rho, int64_t *K)
+{
+  return ka_guard([&]() -> int {
+    if (!K) return fail(KA_EINVAL, "K is NULL");
+    if (N < 1) return fail(KA_EINVAL, "N must be positive");
+    if (!(rho >= 0.0 && rho <= 1.0)) return fail(KA_EINVAL, "density rho must be in [0, 1]");
+    *K = (int64_t)std::floor(rho * (double)N + 0.5);
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_derived(int64_t N, int64_t K, int n_replicas, int n_rows, const int64_t *overlap,
+                          const int64_t *persistence, double *C, double *chi4, double *P)
+{
+  return ka_guard([&]() -> int {
+    if (N < 1 || K < 0 || K > N || n_replicas < 1 || n_rows < 0) return fail(KA_EINVAL, "bad sizes");
+    if ((C || chi4) && !overlap) return fail(KA_EINVAL, "overlap is NULL");
+    if (P && !persistence) return fail(KA_EINVAL, "persistence is NULL");
+    const double nan = std::nan("");
+    const double r = (double)K / (double)N;
+    for (int q = 0; q < n_rows; ++q) {
+      if (C || chi4) {
+        double sum = 0.0, sum2 = 0.0;
+        if (K > 0 && K < N) {
+          for (int b = 0; b < n_replicas; ++b) {
+            const double qb = ((double)overlap[(size_t)q * n_replicas + b] / (double)N - r * r) / (r * (1.0 - r));
+            sum += qb;
+            sum2 += qb * qb;
+          }
+        }
+        const double mean = sum / n_replicas;
+        if (C) C[q] = (K > 0 && K < N) ? mean : nan;
+        if (chi4) chi4[q] = (K > 0 && K < N) ? (double)N * (sum2 / n_replicas - mean * mean) : nan;
+      }
+      if (P) {
+        double sum = 0.0;
+        for (int b = 0; b < n_replicas; ++b) sum += (double)persistence[(size_t)q * n_replicas + b];
+        P[q] = K > 0 ? sum / n_replicas / (double)K : nan;
+      }
+    }
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_g4(int64_t N, int64_t K, int n_replicas, int n_shells, const int64_t *S2,
+                     const int64_t *S11, double *g4)
+{
+  return ka_guard([&]() -> int {
+    if (N < 1 || K < 0 || K > N || n_replicas < 1 || n_shells < 0) return fail(KA_EINVAL, "bad sizes");
+    if (n_shells > 0 && (!S2 || !S11 || !g4)) return fail(KA_EINVAL, "NULL argument");
+    const double r = (double)K / (double)N;
+    const double R = (double)n_replicas;
+    const double norm = (double)N * r * r * (1.0 - r) * (1.0 - r);
+    for (int k = 0; k < n_shells; ++k)
+      g4[k] = (K > 0 && K < N) ? ((double)S2[k] / R - (double)S11[k] / (R * R)) / norm : std::nan("");
+    return KA_OK;
+  });
 }
 
 extern "C" const char *ka_last_error(void) { return g_err.c_str(); }

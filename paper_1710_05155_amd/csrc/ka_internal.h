@@ -162,6 +162,16 @@ struct PairArgs {
   unsigned long long *S11;
 };
 hipError_t launch_pairs(const PairArgs &a, int wpt, hipStream_t s);
+// Graphs without a geometry: out[0] += sum_i Q_i, out[1] += sum_i Q_i^2 with Q_i the number
+// of replicas b with n_i^b(t) n_i^b(0) = 1.
+struct PairGraphArgs {
+  const u64 *n;
+  const u64 *n0;
+  int N;
+  int planes;
+  unsigned long long *out;             // [2]
+};
+hipError_t launch_pairs_graph(const PairGraphArgs &a, int wpt, hipStream_t s);
 int max_lds_bytes();
 
 }  // namespace ka

@@ -1,4 +1,4 @@
-// ka_pairs.hip -- spatial four-point sums on lattices (gfx950).
+// ka_pairs.hip -- spatial four-point sums (gfx950).
 //
 // Method: Boccagna, arXiv 1710.05155, Sec. 2.2 (g4(r, t) and chi4 = sum_r g4) and Sec. 3.3
 // (Phi(r, t) as the popcount of the AND of the words n_i(t), n_i(0), n_j(t), n_j(0)).  With
@@ -109,7 +109,42 @@ __global__ __launch_bounds__(kPairBlock) void k_pairs(PairArgs a)
   }
 }
 
+// Graphs without a geometry (Sec. 3.3: distance 0 for i = j, 1 otherwise): only the per-site
+// replica sums Q_i = sum_b q_i^b are needed, through sum_i Q_i and sum_i Q_i^2 (out[0], out[1]).
+template <int WPT>
+__global__ __launch_bounds__(kPairBlock) void k_pairs_graph(PairGraphArgs a)
+{
+  const int i = (int)blockIdx.x * kPairBlock + (int)threadIdx.x;
+  unsigned q = 0;
+  if (i < a.N) {
+    const size_t plane_words = (size_t)a.N * WPT;
+    for (int p = 0; p < a.planes; ++p)
+#pragma unroll
+      for (int w = 0; w < WPT; ++w) {
+        const size_t off = (size_t)p * plane_words + (size_t)i * WPT + w;
+        q += (unsigned)__popcll(a.n[off] & a.n0[off]);
+      }
+  }
+  // per wave: sum Q <= 64 * 1024 and sum Q^2 <= 64 * 2^20, both within 32 bits
+  const unsigned s1 = wave_sum(q);
+  const unsigned s2 = wave_sum(q * q);
+  if (__lane_id() == 0 && s1) {
+    atomicAdd(&a.out[0], (unsigned long long)s1);
+    atomicAdd(&a.out[1], (unsigned long long)s2);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_pairs_graph(const PairGraphArgs &a, int wpt, hipStream_t s)
+{
+  const dim3 grid((unsigned)((a.N + kPairBlock - 1) / kPairBlock));
+  if (wpt == 2)
+    hipLaunchKernelGGL((k_pairs_graph<2>), grid, dim3(kPairBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_pairs_graph<1>), grid, dim3(kPairBlock), 0, s, a);
+  return hipGetLastError();
+}
 
 hipError_t launch_pairs(const PairArgs &a, int wpt, hipStream_t s)
 {

@@ -33,6 +33,7 @@ SYMBOLS = (
     "ka_batch_wait_all", "ka_batch_set_option", "ka_batch_info", "ka_batch_free",
     "ka_server_create", "ka_server_submit", "ka_server_poll", "ka_server_result", "ka_server_take_sim", "ka_server_release",
     "ka_server_wait_idle", "ka_server_stats", "ka_server_free", "ka_probe_valu",
+    "ka_particles", "ka_derived", "ka_g4",
 )
 
 
@@ -121,6 +122,9 @@ def load():
         "ka_server_stats": ([P, P, P, P, P], I),
         "ka_server_free": ([P], None),
         "ka_probe_valu": ([I, I, I, P, P, P], I),
+        "ka_particles": ([I64, D, P], I),
+        "ka_derived": ([I64, I64, I, I, P, P, P, P, P], I),
+        "ka_g4": ([I64, I64, I, I, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -291,13 +295,6 @@ def ka_observe_pairs(s: Sim, r2_max: int):
     cnt = np.empty(r2_max + 1, dtype=np.int64)
     _check(load().ka_observe_pairs(s.handle, int(r2_max), _ptr(S2), _ptr(S11), _ptr(cnt)))
     return S2, S11, cnt
-
-
-def g4_from_pairs(N: int, K: int, R: int, S2, S11):
-    """g4 per shell: (S2/R - S11/R^2) / (N rho^2 (1-rho)^2), rho = K/N (Sec. 2.2)."""
-    rho = K / N
-    cov = np.asarray(S2, dtype=np.float64) / R - np.asarray(S11, dtype=np.float64) / (R * R)
-    return cov / (N * rho * rho * (1.0 - rho) ** 2)
 
 
 def ka_run(s: Sim, obs_times):
@@ -540,30 +537,38 @@ def ka_probe_valu(kind: int, iters: int = 20000, blocks: int = 4096, stream=None
     return ips.value, lops.value
 
 
-# ------------------------------------------------------------------------------ host helpers
-def k_from_rho(N: int, rho: float) -> int:
-    """Particle number the library uses for density rho: floor(rho*N + 1/2)."""
-    import math
-    return int(math.floor(float(rho) * float(N) + 0.5))
+# ------------------------------------------------------------------------------ host-side quantities
+def ka_particles(N: int, rho: float) -> int:
+    """Particle number the library uses for density rho (ka_particles)."""
+    K = ctypes.c_int64()
+    _check(load().ka_particles(int(N), float(rho), ctypes.byref(K)))
+    return K.value
 
 
-def derived_observables(N: int, K: int, overlap, persistence):
-    """Replica averages of the integer counts (Sec. 2.2): q_b = (overlap_b/N - r^2)/(r(1-r))
-    with r = K/N, C = mean q_b, chi4 = N*(mean q_b^2 - (mean q_b)^2), and the mean
-    persistence fraction P = mean persistence_b / K.  Rows of a [n_obs, R] array give one
-    value per observation time."""
-    ov = np.atleast_2d(np.asarray(overlap, dtype=np.float64))
-    pe = np.atleast_2d(np.asarray(persistence, dtype=np.float64))
-    r = K / N
-    if 0 < K < N:
-        q = (ov / N - r * r) / (r * (1.0 - r))
-        C = q.mean(axis=1)
-        chi4 = N * ((q * q).mean(axis=1) - q.mean(axis=1) ** 2)
-    else:
-        C = np.full(ov.shape[0], np.nan)
-        chi4 = np.full(ov.shape[0], np.nan)
-    P = pe.mean(axis=1) / K if K > 0 else np.full(pe.shape[0], np.nan)
+def ka_derived(N: int, K: int, overlap, persistence=None):
+    """(C, chi4, P) per row of the [n_rows, R] counts (ka_derived); P is None without
+    persistence."""
+    ov = np.ascontiguousarray(np.atleast_2d(np.asarray(overlap, dtype=np.int64)))
+    rows, R = ov.shape
+    pe = None
+    if persistence is not None:
+        pe = np.ascontiguousarray(np.atleast_2d(np.asarray(persistence, dtype=np.int64)))
+        assert pe.shape == ov.shape
+    C = np.empty(rows)
+    chi4 = np.empty(rows)
+    P = np.empty(rows) if pe is not None else None
+    _check(load().ka_derived(int(N), int(K), R, rows, _ptr(ov), _ptr(pe), _ptr(C), _ptr(chi4), _ptr(P)))
     return C, chi4, P
+
+
+def ka_g4(N: int, K: int, n_replicas: int, S2, S11):
+    """g4 per shell from the sums of ka_observe_pairs (ka_g4)."""
+    a = np.ascontiguousarray(np.asarray(S2, dtype=np.int64))
+    b = np.ascontiguousarray(np.asarray(S11, dtype=np.int64))
+    assert a.shape == b.shape and a.ndim == 1
+    out = np.empty(a.shape[0])
+    _check(load().ka_g4(int(N), int(K), int(n_replicas), a.shape[0], _ptr(a), _ptr(b), _ptr(out)))
+    return out
 
 
 from .workloads import log_time_grid  # noqa: E402,F401  (observation grid recipe)

@@ -28,7 +28,7 @@ def test_largest_lattice(oracle, d, L):
     g = ka.ka_graph_lattice(d, L)
     assert g.N == 1 << 30
     m, rho, seed, R = d, 0.85, 11, 64
-    K = ka.k_from_rho(g.N, rho)
+    K = ka.ka_particles(g.N, rho)
     _say(f"max size: d={d} L={L} N=2^30 R={R} K={K}")
     a = ka.ka_init(g, m, rho, seed, R)
     t, dens, ov, pers = ka.ka_observe(a)

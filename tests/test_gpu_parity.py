@@ -270,9 +270,11 @@ def test_pair_sums_parity(oracle, d, L, m, rho, R, sweeps, r2_max):
     assert np.array_equal(S2, oS2) and np.array_equal(S11, oS11)
 
 
-def test_pair_sums_cover_chi4_gpu():
+def test_pair_sums_cover_chi4_gpu(oracle):
     """All displacements of 3D L=16 x 256 replicas: sum S2 = sum_b overlap_b^2, sum S11 =
-    (sum_b overlap_b)^2, S2[0] = sum_b overlap_b, so sum_r g4(r) = chi4."""
+    (sum_b overlap_b)^2, S2[0] = sum_b overlap_b, so the library's g4 (ka_g4) sums to the
+    chi4 that the oracle's own formula gives for the oracle's overlaps of the same run, and
+    the library's ka_derived equals the oracle's formula too."""
     g = ka.ka_graph_lattice(3, 16)
     _say("pair sums full coverage 3D L=16")
     sim = ka.ka_init(g, 3, 0.75, 5, 256)
@@ -283,9 +285,48 @@ def test_pair_sums_cover_chi4_gpu():
     assert S2.sum() == int((ov.astype(object) ** 2).sum())
     assert S11.sum() == int(ov.sum()) ** 2
     assert S2[0] == int(ov.sum())
-    g4 = ka.g4_from_pairs(g.N, sim.K, 256, S2, S11)
-    _, chi4, _ = ka.derived_observables(g.N, sim.K, ov, pers)
-    assert abs(g4.sum() - chi4[0]) < 1e-9 * max(1.0, abs(chi4[0]))
+    orc = oracle.Sim(oracle.lattice(3, 16), 3, sim.K, 5, range(256))
+    orc.sweep(20)
+    _, o_ov, o_pers = orc.observe()
+    assert np.array_equal(ov, o_ov) and np.array_equal(pers, o_pers)
+    oC, o_chi4, oP = oracle.derived(g.N, sim.K, o_ov, o_pers)
+    g4 = ka.ka_g4(g.N, sim.K, 256, S2, S11)
+    assert abs(g4.sum() - o_chi4) < 1e-9 * max(1.0, abs(o_chi4))
+    C, chi4, P = ka.ka_derived(g.N, sim.K, ov, pers)
+    assert abs(C[0] - oC) < 1e-12 and abs(chi4[0] - o_chi4) < 1e-9 * max(1.0, abs(o_chi4))
+    assert abs(P[0] - oP) < 1e-12
+
+
+GRAPH_PAIR_CASES = [
+    # kind, N or (d, L, M), z, m, rho, R, sweeps, r2_max
+    ("rrg", 300, 4, 2, 0.6, 64, 5, 0),
+    ("rrg", 500, 3, 1, 0.5, 128, 4, 1),
+    ("rrg", 1000, 5, 3, 0.7, 192, 3, 6),
+    ("layered", (2, 8, 3), 4, 2, 0.65, 64, 6, 2),
+    ("rrg", 20000, 4, 2, 0.75, 64, 2, 1),       # global path
+]
+
+
+@pytest.mark.parametrize("kind,size,z,m,rho,R,sweeps,r2_max", GRAPH_PAIR_CASES)
+def test_pair_sums_graph_parity(oracle, kind, size, z, m, rho, R, sweeps, r2_max):
+    """Graphs without a geometry use the distance 0 for i = j and 1 otherwise (Sec. 3.3):
+    the library's shells equal the oracle's explicit pair loop."""
+    if kind == "rrg":
+        g = ka.ka_graph_rrg(size, z, 31)
+    else:
+        g = ka.ka_graph_layered(*size, 31)
+    adj, _, _, _ = ka.ka_graph_export(g)
+    og = oracle.graph_from_adjacency(adj)
+    K = oracle.k_from_rho(og.N, rho)
+    _say(f"graph pair sums {kind} {size} z={z} R={R} r2_max={r2_max}")
+    sim = ka.ka_init_k(g, m, K, 17, R)
+    ka.ka_sweep(sim, sweeps)
+    S2, S11, cnt = ka.ka_observe_pairs(sim, r2_max)
+    orc = oracle.Sim(og, m, K, 17, range(R))
+    orc.sweep(sweeps)
+    oS2, oS11, ocnt = oracle.pair_sums_graph(orc.occ, orc.occ0, r2_max)
+    assert np.array_equal(cnt, ocnt)
+    assert np.array_equal(S2, oS2) and np.array_equal(S11, oS11)
 
 
 def test_pair_sums_full_workload_properties():
@@ -314,7 +355,7 @@ def test_graph_schedule_reused_and_outlives_graph(oracle):
     g = ka.ka_graph_rrg(N, z, seed)
     adj, _, _, _ = ka.ka_graph_export(g)
     og = oracle.graph_from_adjacency(adj)
-    K = ka.k_from_rho(N, 0.6)
+    K = ka.ka_particles(N, 0.6)
     _say(f"schedule reuse: RRG N={N} z={z} K={K} R={R}")
     sims = [ka.ka_init_k(g, m, K, s, R) for s in (3, 4)]
     ka.load().ka_graph_free(g.handle)
@@ -493,4 +534,32 @@ def test_lds_graph_chunk_boundaries(oracle, z, R):
     for k, b in enumerate(replicas):
         assert np.array_equal(((n[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.occ[k])
         assert np.array_equal(((f[b // 64] >> np.uint64(b % 64)) & np.uint64(1)).astype(np.uint8), orc.moved[k])
+    sim.free()
+
+
+@pytest.mark.parametrize("z,R", [(3, 64), (4, 64), (3, 192), (4, 192)])
+def test_lds_graph_two_edges_per_thread(oracle, z, R):
+    """Random regular graphs of 8192 vertices fit the LDS-resident sweep with classes of more
+    than 1024 edges, so a thread takes a second edge slot of every large class.  With one and
+    with three word planes (one workgroup each), across chunks of acceptance words generated
+    ahead, every replica matches the oracle at every observation and in the final state."""
+    N = 8192
+    g = ka.ka_graph_rrg(N, z, 29)
+    oadj, _ = oracle.rrg_adjacency(N, z, 29)
+    og = oracle.graph_from_adjacency(oadj)
+    _, _, _, ec = ka.ka_graph_export(g)
+    assert np.bincount(ec).max() > 1024
+    K = oracle.k_from_rho(N, 0.6)
+    chunk = min(20000, (8 << 20) // (g.E * (R // 64) * 8))
+    _say(f"LDS graph two slots z={z} R={R} chunk={chunk}")
+    sim = ka.ka_init_k(g, 2, K, 6, R)
+    ka.ka_set_option(sim, ka.KA_OPT_PATH, 2)
+    orc = oracle.Sim(og, 2, K, 6, range(R))
+    times = [1, chunk - 1, chunk, chunk + 1, 2 * chunk, 2 * chunk + 5]
+    dens, ov, pers = ka.ka_run(sim, times)
+    for q, t in enumerate(times):
+        orc.sweep(t - orc.t)
+        od, oo, op = orc.observe()
+        assert np.array_equal(dens[q], od) and np.array_equal(ov[q], oo) and np.array_equal(pers[q], op), t
+    _state_equal(sim, orc)
     sim.free()

@@ -1,6 +1,8 @@
 """Serving with continuous batching: jobs submitted while others run are admitted as slots
 and device memory free up, share the batch's step kernels, and each job's observations and
-final state are bit-identical to running it alone."""
+final state are bit-identical to running it alone; four of them (2D, 3D with four words per
+site, a random regular graph, and one admitted while others run) are also compared with the
+oracle at every observation and in the final state."""
 import random
 import time
 
@@ -77,8 +79,41 @@ def _run_server(graphs, budget, max_active, jitter):
     return out, stats
 
 
+# Served jobs also compared with the oracle directly: a 2D lattice, a 3D lattice with four
+# words per site, a random regular graph, and the last job, which with 3 slots is admitted
+# only after earlier jobs complete, while others still run.
+ORACLE_JOBS = (0, 2, 3, 11)
+
+
+def _oracle_graph(oracle, graphs, key):
+    if key[0] == "lat":
+        return oracle.lattice(key[1], key[2])
+    adj, _ = oracle.rrg_adjacency(key[1], key[2], 40 + key[1])
+    exported, _, _, _ = ka.ka_graph_export(graphs[key])
+    assert np.array_equal(adj, exported)
+    return oracle.graph_from_adjacency(adj)
+
+
+def _oracle_equal(oracle, graphs, job, res, state):
+    key, m, rho, R, seed, sweeps, obs = job
+    og = _oracle_graph(oracle, graphs, key)
+    orc = oracle.Sim(og, m, oracle.k_from_rho(og.N, rho), seed, range(R))
+    for q, t in enumerate(obs if obs is not None else [sweeps]):
+        orc.sweep(t - orc.t)
+        d, o, p = orc.observe()
+        assert np.array_equal(res["density"][q], d), t
+        assert np.array_equal(res["overlap"][q], o), t
+        assert np.array_equal(res["persistence"][q], p), t
+    orc.sweep(sweeps - orc.t)
+    n, n0, f, t = state
+    assert t == sweeps
+    assert np.array_equal(n, oracle.pack(orc.occ))
+    assert np.array_equal(n0, oracle.pack(orc.occ0))
+    assert np.array_equal(f, oracle.pack(orc.moved))
+
+
 @pytest.mark.parametrize("budget,max_active,jitter", [(1 << 34, 64, True), (1 << 34, 3, False)])
-def test_served_jobs_equal_solo(graphs, budget, max_active, jitter):
+def test_served_jobs_equal_solo(oracle, graphs, budget, max_active, jitter):
     _say(f"serve budget={budget} max_active={max_active}")
     served, stats = _run_server(graphs, budget, max_active, jitter)
     assert stats["jobs_done"] == len(JOBS)
@@ -91,6 +126,11 @@ def test_served_jobs_equal_solo(graphs, budget, max_active, jitter):
         for a, b in zip(state, solo_state):
             assert np.array_equal(np.asarray(a), np.asarray(b)), k
         assert res["latency_s"] >= res["wait_s"] >= 0.0
+    if max_active == 3:
+        assert served[ORACLE_JOBS[-1]][0]["wait_s"] > 0.0    # admitted while others ran
+    for k in ORACLE_JOBS:
+        _say(f"serve: job {k} against the oracle")
+        _oracle_equal(oracle, graphs, JOBS[k], *served[k])
 
 
 def test_admission_by_footprint(graphs):

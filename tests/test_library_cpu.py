@@ -17,7 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_header_symbols_exported():
     with open(os.path.join(ROOT, "include", "ka.h")) as fh:
         header = fh.read()
-    declared = set(re.findall(r"\b(ka_[a-z_]+)\s*\(", header))
+    declared = set(re.findall(r"\b(ka_[a-z0-9_]+)\s*\(", header))
     assert declared == set(ka.SYMBOLS)
     lib = ctypes.CDLL(ka.LIB_PATH)
     for name in declared:
@@ -151,3 +151,33 @@ def test_product_never_imports_the_oracle():
             with open(os.path.join(dirpath, name)) as fh:
                 text = fh.read()
             assert not re.search(r"\boracle\b|liboracle|ka_oracle", text), os.path.join(dirpath, name)
+
+
+def test_host_derived_quantities_match_oracle(oracle):
+    """ka_particles, ka_derived and ka_g4 are host code (no GPU): they equal the oracle's
+    formulas (Sec. 3.1 particle number, Sec. 2.2 C, chi4, P and g4) on random counts,
+    including the round-half-up ties of K and the K = 0 / K = N cases."""
+    for N, rho in [(64 ** 2, 0.70), (128 ** 3, 0.85), (2, 0.25), (8, 0.3125), (16, 0.90625),
+                   (10, 0.0), (10, 1.0), (1 << 20, 0.55)]:
+        assert ka.ka_particles(N, rho) == oracle.k_from_rho(N, rho)
+    rng = np.random.default_rng(2)
+    for N, K, R in [(4096, 2867, 64), (2 ** 21, 1782579, 256), (100, 1, 128)]:
+        ov = rng.integers(0, K + 1, size=(5, R))
+        pe = np.minimum(ov, rng.integers(0, K + 1, size=(5, R)))
+        C, chi4, P = ka.ka_derived(N, K, ov, pe)
+        for q in range(5):
+            oC, ochi4, oP = oracle.derived(N, K, ov[q], pe[q])
+            assert abs(C[q] - oC) <= 1e-12 * max(1.0, abs(oC))
+            assert abs(chi4[q] - ochi4) <= 1e-9 * max(1.0, abs(ochi4))
+            assert abs(P[q] - oP) <= 1e-12
+        S2 = rng.integers(0, 1 << 40, size=7)
+        S11 = rng.integers(0, 1 << 50, size=7)
+        assert np.allclose(ka.ka_g4(N, K, R, S2, S11), oracle.g4_from_pairs(N, K, R, S2, S11), rtol=1e-12, atol=0)
+    C, chi4, P = ka.ka_derived(10, 0, np.zeros((1, 64), dtype=np.int64), np.zeros((1, 64), dtype=np.int64))
+    assert np.isnan(C[0]) and np.isnan(chi4[0]) and np.isnan(P[0])
+    C, chi4, P = ka.ka_derived(10, 10, np.full((1, 64), 10), np.zeros((1, 64), dtype=np.int64))
+    assert np.isnan(C[0]) and np.isnan(chi4[0]) and P[0] == 0.0
+    with pytest.raises(ka.KaError):
+        ka.ka_particles(10, 1.5)
+    with pytest.raises(ka.KaError):
+        ka.ka_derived(10, 11, np.zeros((1, 64), dtype=np.int64))

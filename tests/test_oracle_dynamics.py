@@ -414,3 +414,29 @@ def test_pair_sums_cover_chi4(oracle, d, L):
     g4 = oracle.g4_from_pairs(g.N, K, 128, S2, S11)
     _, chi4, _ = oracle.derived(g.N, K, ov, pers)
     assert abs(g4.sum() - chi4) < 1e-9 * max(1.0, abs(chi4))
+
+
+@pytest.mark.parametrize("N,z,R", [(12, 3, 64), (20, 4, 128)])
+def test_pair_sums_graph_brute_force_tiny(oracle, N, z, R):
+    """Graphs without a geometry (Sec. 3.3: distance 0 for i = j, 1 otherwise): the closed
+    form used at any size equals the explicit loop over every ordered site pair; the shells
+    cover all pairs, so sum S2 = sum_b overlap_b^2, sum S11 = (sum_b overlap_b)^2, and
+    sum_r g4(r) = chi4."""
+    adj, _ = oracle.rrg_adjacency(N, z, 5)
+    g = oracle.graph_from_adjacency(adj)
+    K = oracle.k_from_rho(N, 0.5)
+    s = oracle.Sim(g, 1, K, 3, range(R))
+    s.sweep(3)
+    for r2_max in (0, 1, 3):
+        got = oracle.pair_sums_graph(s.occ, s.occ0, r2_max)
+        want = oracle.pair_sums_graph_bruteforce(s.occ, s.occ0, r2_max)
+        for a, b in zip(got, want):
+            assert np.array_equal(a, b), r2_max
+    S2, S11, count = oracle.pair_sums_graph(s.occ, s.occ0, 1)
+    _, ov, pers = s.observe()
+    assert count.tolist() == [1, N - 1]
+    assert S2.sum() == int((ov.astype(np.int64) ** 2).sum()) and S2[0] == int(ov.sum())
+    assert S11.sum() == int(ov.sum()) ** 2
+    g4 = oracle.g4_from_pairs(N, K, R, S2, S11)
+    _, chi4, _ = oracle.derived(N, K, ov, pers)
+    assert abs(g4.sum() - chi4) < 1e-9 * max(1.0, abs(chi4))
