@@ -313,10 +313,11 @@ def test_pair_sums_graph_parity(oracle, kind, size, z, m, rho, R, sweeps, r2_max
     the library's shells equal the oracle's explicit pair loop."""
     if kind == "rrg":
         g = ka.ka_graph_rrg(size, z, 31)
+        adj, _, _, _ = ka.ka_graph_export(g)
+        og = oracle.graph_from_adjacency(adj)
     else:
         g = ka.ka_graph_layered(*size, 31)
-    adj, _, _, _ = ka.ka_graph_export(g)
-    og = oracle.graph_from_adjacency(adj)
+        og = oracle.layered(*size, 31)       # classes projected from the lattice (L % 4 == 0)
     K = oracle.k_from_rho(og.N, rho)
     _say(f"graph pair sums {kind} {size} z={z} R={R} r2_max={r2_max}")
     sim = ka.ka_init_k(g, m, K, 17, R)
