@@ -142,6 +142,18 @@ int ka_sweep(ka_sim *s, int64_t n_sweeps);
 int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
                int64_t *persistence);
 
+/* ka_observe for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same counts, accumulated in a
+ * fixed device scratch array of the library (3 x 8192 counts, 192 KiB, one per device, held
+ * until the process ends) instead of the sim's own observation buffer, which ka_observe
+ * allocates on first use.  Calls no hipMalloc or hipFree.  At most 8192 replicas (KA_EINVAL
+ * beyond).  Every call on a device shares that scratch: calls that overlap on one device
+ * (from several host threads, or on several streams) race and must be serialised by the
+ * caller.  The scratch is cleared by a kernel at the start of each call.  Synchronises the
+ * sim's stream. */
+int ka_observe_noalloc(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
+                       int64_t *persistence);
+
 /* Spatial four-point sums at the current t (Sec. 2.2 g4 and chi4 = sum_r g4; Sec. 3.3
  * Phi(r, t) as the popcount of the AND of n_i(t), n_i(0), n_j(t), n_j(0)), with
  * q_i^b = n_i^b(t) n_i^b(0), over ordered site pairs (i, j) grouped in shells r2:

@@ -1141,6 +1141,13 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
     s->wpt = (s->W % 2 == 0) ? 2 : 1;
     s->planes = s->W / s->wpt;
     (void)hipGetDevice(&s->device);
+    {
+      const hipError_t se = ka::observe_scratch_setup(s->device);
+      if (se != hipSuccess) {
+        delete s;
+        return hip_fail(se, "observation scratch");
+      }
+    }
     if (hip_stream) {
       s->stream = (hipStream_t)hip_stream;
     } else {
@@ -1353,6 +1360,46 @@ extern "C" int ka_observe(ka_sim *s, int64_t *t, int64_t *density, int64_t *over
     const int64_t now = s->t;
     rc = ka_run(s, &now, 1, density, overlap, persistence);
     if (rc) return rc;
+    if (t) *t = s->t;
+    return KA_OK;
+  });
+}
+
+extern "C" int ka_observe_noalloc(ka_sim *s, int64_t *t, int64_t *density, int64_t *overlap,
+                                  int64_t *persistence)
+{
+  return ka_guard([&]() -> int {
+    int rc = check_sim(s);
+    if (rc) return rc;
+    if (s->R > ka::kObserveScratchReplicas)
+      return fail(KA_EINVAL, "ka_observe_noalloc supports at most %d replicas (got %d)",
+                  ka::kObserveScratchReplicas, s->R);
+    DeviceGuard dg(s->device);
+    unsigned long long *scr = ka::observe_scratch(s->device);
+    if (!scr) return fail(KA_ESTATE, "observation scratch not set up on device %d", s->device);
+    const int words = 3 * s->R;
+    hipError_t e = ka::launch_fill_u64(scr, words, 0ull, s->stream);
+    if (e == hipSuccess) {
+      ka::ObserveArgs a{};
+      a.n = s->n;
+      a.n0 = s->n0;
+      a.f = s->f;
+      a.N = (int)s->N;
+      a.planes = s->planes;
+      a.R = s->R;
+      a.out = scr;
+      a.rows = 1;
+      a.row_stride = 0;
+      e = ka::launch_observe(a, s->wpt, s->stream);
+    }
+    // the counts (below 2^63) go straight into the caller's arrays: no host buffer either
+    int64_t *dst[3] = {density, overlap, persistence};
+    for (int o = 0; o < 3 && e == hipSuccess; ++o)
+      if (dst[o])
+        e = hipMemcpyAsync(dst[o], scr + (size_t)o * s->R, (size_t)s->R * sizeof(int64_t), hipMemcpyDeviceToHost,
+                           s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "ka_observe_noalloc");
     if (t) *t = s->t;
     return KA_OK;
   });

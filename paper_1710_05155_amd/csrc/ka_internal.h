@@ -135,6 +135,15 @@ hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, in
                             size_t lds_bytes, hipStream_t s);
 hipError_t launch_init(const InitArgs &a, int R, int wpt, hipStream_t s);
 hipError_t launch_observe(const ObserveArgs &a, int wpt, hipStream_t s);
+// Fixed device scratch of the observation entry point that allocates nothing: 3 counts per
+// replica for up to kObserveScratchReplicas replicas.  observe_scratch_setup takes its address
+// on the current device (once per device; called by ka_init); observe_scratch returns it
+// (null before the setup).
+constexpr int kObserveScratchReplicas = 8192;
+constexpr int kObserveScratchWords = 3 * kObserveScratchReplicas;
+hipError_t observe_scratch_setup(int device);
+unsigned long long *observe_scratch(int device);
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s);
 size_t sweep_lds_bytes(int N, int wpt);
 // Edge slots per thread of the LDS lattice sweep (edges per class over its 1024 threads).
 int lds_lattice_slots(int d, int P);

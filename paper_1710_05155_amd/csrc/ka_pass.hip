@@ -1,7 +1,13 @@
 // ka_pass.hip -- global-memory class passes, observables and initial state (gfx950).
 //
 // Method: Boccagna, arXiv 1710.05155; the per-edge bit logic lives in ka_device.h.
+#include <mutex>
+
 #include "ka_device.h"
+
+// Fixed device scratch of the observation entry point that allocates nothing (see
+// observe_scratch_setup below): one copy per device, held until the process ends.
+static __device__ __align__(256) unsigned long long scratch[ka::kObserveScratchWords];
 
 namespace ka {
 namespace {
@@ -394,6 +400,53 @@ hipError_t launch_init(const InitArgs &a, int R, int wpt, hipStream_t s)
     hipLaunchKernelGGL((k_init_fill<2>), dim3((unsigned)bx, (unsigned)planes), dim3(256), 0, s, a);
   else
     hipLaunchKernelGGL((k_init_fill<1>), dim3((unsigned)bx, (unsigned)planes), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Fixed scratch for the observation entry point that allocates nothing (ka_observe_noalloc):
+// the per-replica counts accumulate here instead of in a sim's own buffer.  One copy per
+// device, held until the process ends; every call on a device shares it.
+// ------------------------------------------------------------------------------------
+namespace {
+
+__global__ void k_fill_u64(unsigned long long *p, int n, unsigned long long v)
+{
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) p[i] = v;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long *g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+hipError_t observe_scratch_setup(int device)
+{
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  // the array's name is only a host-side stand-in: the device address comes from the runtime,
+  // taken with this device current
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(::scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[device] = static_cast<unsigned long long *>(ptr);
+  return hipSuccess;
+}
+
+unsigned long long *observe_scratch(int device)
+{
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
+
+hipError_t launch_fill_u64(unsigned long long *p, int n, unsigned long long v, hipStream_t s)
+{
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

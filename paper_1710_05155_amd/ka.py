@@ -33,7 +33,7 @@ SYMBOLS = (
     "ka_batch_wait_all", "ka_batch_set_option", "ka_batch_info", "ka_batch_free",
     "ka_server_create", "ka_server_submit", "ka_server_poll", "ka_server_result", "ka_server_take_sim", "ka_server_release",
     "ka_server_wait_idle", "ka_server_stats", "ka_server_free", "ka_probe_valu",
-    "ka_particles", "ka_derived", "ka_g4",
+    "ka_particles", "ka_derived", "ka_g4", "ka_observe_noalloc",
 )
 
 
@@ -93,6 +93,7 @@ def load():
         "ka_init_k": ([P, I, I64, U64, I, P, PP], I),
         "ka_sweep": ([P, I64], I),
         "ka_observe": ([P, P, P, P, P], I),
+        "ka_observe_noalloc": ([P, P, P, P, P], I),
         "ka_run": ([P, P, I, P, P, P], I),
         "ka_observe_pairs": ([P, I, P, P, P], I),
         "ka_get_state": ([P, P, P, P, P], I),
@@ -285,6 +286,16 @@ def ka_observe(s: Sim):
     ov = np.empty(s.R, dtype=np.int64)
     pers = np.empty(s.R, dtype=np.int64)
     _check(load().ka_observe(s.handle, ctypes.byref(t), _ptr(dens), _ptr(ov), _ptr(pers)))
+    return t.value, dens, ov, pers
+
+
+def ka_observe_noalloc(s: Sim):
+    """ka_observe through the library's fixed device scratch (no device allocation)."""
+    t = ctypes.c_int64()
+    dens = np.empty(s.R, dtype=np.int64)
+    ov = np.empty(s.R, dtype=np.int64)
+    pers = np.empty(s.R, dtype=np.int64)
+    _check(load().ka_observe_noalloc(s.handle, ctypes.byref(t), _ptr(dens), _ptr(ov), _ptr(pers)))
     return t.value, dens, ov, pers
 
 
