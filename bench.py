@@ -90,10 +90,16 @@ def measured_traffic(kernel_sources, counters_file, key="traffic_bytes_per_launc
 
 
 def obs_grid(w):
+    """Observation times of one job; the last one is the job's final sweep, so that a job
+    always runs exactly w["sweeps"] sweeps."""
     from paper_1710_05155_amd import workloads
     if "obs_every" in w:
-        return list(range(0, w["sweeps"] + 1, w["obs_every"]))
-    return workloads.log_time_grid(w["sweeps"])
+        grid = list(range(0, w["sweeps"] + 1, w["obs_every"]))
+    else:
+        grid = workloads.log_time_grid(w["sweeps"])
+    if grid[-1] != w["sweeps"]:
+        grid.append(w["sweeps"])
+    return grid
 
 
 def cpu_baseline(w, seconds_target=15.0):

@@ -15,6 +15,8 @@
 // All hot-path work is integer bit logic: there is no dense contraction, so no MFMA.
 #pragma once
 
+#include <type_traits>
+
 #include "ka_internal.h"
 
 namespace ka {
@@ -340,13 +342,49 @@ __device__ __forceinline__ void lattice_stencil(const LatticeGeom &g, const Site
   }
 }
 
+// Optional summary of the moved-ever words: bit (base + element) of `bits` is set once every
+// word of the element's f is all ones, after which f can no longer change there and the
+// exchange skips reading it.  A clear bit only means "not known to be full": f is read as
+// usual.  NoSat disables the summary (f is always read where an exchange happens).
+struct NoSat {};
+struct FSat {
+  uint32_t *bits;
+  int base;    // bit index of element 0 of this plane
+};
+
+// f |= d at element i, reading f only if the summary does not already know it is full; the
+// store happens only when f gains a bit, and a store that makes f all ones sets the summary
+// bit (fire-and-forget atomic: other bits of the word belong to other sites).
+template <int WPT, typename SatT>
+__device__ __forceinline__ void moved_ever_or(u64 *fb, int i, const u64 (&d)[WPT], const Elem<WPT> &fi,
+                                              SatT sat)
+{
+  Elem<WPT> fn = fi;
+  u64 gain = 0, full = ~0ull;
+#pragma unroll
+  for (int w = 0; w < WPT; ++w) {
+    gain |= d[w] & ~fn.w[w];
+    fn.w[w] |= d[w];
+    full &= fn.w[w];
+  }
+  if (gain) {
+    st<WPT>(fb, i, fn);
+    if constexpr (!std::is_same<SatT, NoSat>::value) {
+      if (full == ~0ull) {
+        const unsigned b = (unsigned)(sat.base + i);
+        __hip_atomic_fetch_or(sat.bits + (b >> 5), 1u << (b & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+  }
+}
+
 // The exchange across one edge (i, j) on the plane at base nb (moved-ever words at fb;
 // global memory or LDS), given the element indices of i, j and of their K neighbours other
 // than the partner; draw(r) supplies the edge's acceptance words once the state loads are
 // issued.  Shared by every path.
-template <int K, int WPT, typename Draw>
+template <int K, int WPT, typename Draw, typename SatT = NoSat>
 __device__ __forceinline__ void edge_update_with(u64 *nb, u64 *fb, int i, int j, const int (&ii)[K],
-                                                 const int (&jj)[K], int m, Draw draw)
+                                                 const int (&jj)[K], int m, Draw draw, SatT sat = SatT{})
 {
   Elem<WPT> ni = ld<WPT>(nb, i);
   Elem<WPT> nj = ld<WPT>(nb, j);
@@ -355,6 +393,13 @@ __device__ __forceinline__ void edge_update_with(u64 *nb, u64 *fb, int i, int j,
   for (int k = 0; k < K; ++k) {
     xi[k] = ld<WPT>(nb, ii[k]);
     xj[k] = ld<WPT>(nb, jj[k]);
+  }
+  bool full_i = false, full_j = false;
+  if constexpr (!std::is_same<SatT, NoSat>::value) {
+    // issued with the state loads; the summary is small and stays in L2
+    const unsigned bi = (unsigned)(sat.base + i), bj = (unsigned)(sat.base + j);
+    full_i = (sat.bits[bi >> 5] >> (bi & 31u)) & 1u;
+    full_j = (sat.bits[bj >> 5] >> (bj & 31u)) & 1u;
   }
   u64 r[WPT];
   draw(r);
@@ -367,33 +412,27 @@ __device__ __forceinline__ void edge_update_with(u64 *nb, u64 *fb, int i, int j,
     st<WPT>(nb, i, ni);
     st<WPT>(nb, j, nj);
     // f only gains a bit the first time a site changes in a replica, so it is stored
-    // only then: over a run a word is rewritten at most 64 times.
-    Elem<WPT> fi = ld<WPT>(fb, i);
-    Elem<WPT> fj = ld<WPT>(fb, j);
-    u64 new_i = 0, new_j = 0;
-#pragma unroll
-    for (int w = 0; w < WPT; ++w) {
-      new_i |= d[w] & ~fi.w[w];
-      new_j |= d[w] & ~fj.w[w];
-      fi.w[w] |= d[w];
-      fj.w[w] |= d[w];
-    }
-    if (new_i) st<WPT>(fb, i, fi);
-    if (new_j) st<WPT>(fb, j, fj);
+    // only then: over a run a word is rewritten at most 64 times.  Both loads are issued
+    // before either is used.
+    Elem<WPT> fi, fj;
+    if (!full_i) fi = ld<WPT>(fb, i);
+    if (!full_j) fj = ld<WPT>(fb, j);
+    if (!full_i) moved_ever_or<WPT>(fb, i, d, fi, sat);
+    if (!full_j) moved_ever_or<WPT>(fb, j, d, fj, sat);
   }
 }
 
 // The same exchange for the edge with canonical id e, class c, sweep t: its acceptance words
 // are drawn here.
-template <int K, int WPT>
+template <int K, int WPT, typename SatT = NoSat>
 __device__ __forceinline__ void edge_update(u64 *nb, u64 *fb, int i, int j, const int (&ii)[K],
                                             const int (&jj)[K], uint32_t e, int plane, int m,
                                             uint32_t t, uint32_t c, uint32_t k0, uint32_t k1,
-                                            int noise)
+                                            int noise, SatT sat = SatT{})
 {
   edge_update_with<K, WPT>(nb, fb, i, j, ii, jj, m, [&](u64 (&r)[WPT]) {
     accept_words<WPT>(t, c, e, plane, k0, k1, noise, r);
-  });
+  }, sat);
 }
 
 // Element indices and canonical id of the lattice edge (si, si + e_MU): i, j, the 2D-1
@@ -436,10 +475,11 @@ __device__ __forceinline__ void lattice_edge(u64 *nb, u64 *fb, const LatticeGeom
 // its neighbour lists in slot-major arrays of stride `stride`: slots 0..z-2 hold the
 // neighbours of u other than v, slots z-1..2z-3 those of v other than u.  All 2z state
 // words are gathered at once, with no dependent adjacency-row load in front of them.
-template <int Z, int WPT>
+template <int Z, int WPT, typename SatT = NoSat>
 __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int4 *edges, const int32_t *nbr,
                                            size_t stride, int k, int plane, int m, uint32_t t,
-                                           uint32_t c, uint32_t k0, uint32_t k1, int noise)
+                                           uint32_t c, uint32_t k0, uint32_t k1, int noise,
+                                           SatT sat = SatT{})
 {
   constexpr int K = Z - 1;
   const int4 E = edges[k];
@@ -449,7 +489,7 @@ __device__ __forceinline__ void graph_edge(u64 *nb, u64 *fb, const int4 *edges, 
     iu[q] = nbr[(size_t)q * stride + (size_t)k];
     iv[q] = nbr[(size_t)(K + q) * stride + (size_t)k];
   }
-  edge_update<K, WPT>(nb, fb, E.x, E.y, iu, iv, (uint32_t)E.z, plane, m, t, c, k0, k1, noise);
+  edge_update<K, WPT>(nb, fb, E.x, E.y, iu, iv, (uint32_t)E.z, plane, m, t, c, k0, k1, noise, sat);
 }
 
 // ------------------------------------------------------------------------------------

@@ -474,6 +474,16 @@ namespace {
 
 size_t state_bytes(int64_t N, int R) { return (size_t)3 * (size_t)N * (size_t)(R / 64) * 8u; }
 
+// Summary of full moved-ever elements of a general-graph sim (one bit per element and plane,
+// in 32-bit words); 0 when the bit index would not fit 32 bits (the summary is then off).
+size_t fsat_bytes(int64_t N, int R)
+{
+  const int W = R / 64, wpt = (W % 2 == 0) ? 2 : 1;
+  const uint64_t bits = (uint64_t)N * (uint64_t)(W / wpt);
+  if (bits >= (1ull << 32)) return 0;
+  return (size_t)((bits + 31) / 32) * 4u;
+}
+
 size_t graph_device_bytes(const ka_graph *g)
 {
   if (g->lattice) return 0;
@@ -491,6 +501,8 @@ void free_device(ka_sim *s)
   (void)hipFree(s->edges);
   (void)hipFree(s->class_start_d);
   (void)hipFree(s->site_of);
+  (void)hipFree(s->fsat);
+  s->fsat = nullptr;
   (void)hipFree(s->thr_u);
   (void)hipFree(s->thr_i);
   (void)hipFree(s->err);
@@ -668,6 +680,7 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
     a.key0 = k0;
     a.key1 = k1;
     a.noise = s->noise;
+    a.fsat = s->fsat;
     err = a.count > 0 ? ka::launch_pass_graph(a, s->z, s->m, s->wpt, s->stream) : hipSuccess;
   }
   if (timed) {
@@ -1095,7 +1108,8 @@ extern "C" int ka_footprint(const ka_graph *g, int n_replicas, size_t *device_by
     if (!g || !device_bytes) return fail(KA_EINVAL, "NULL argument");
     if (n_replicas <= 0 || n_replicas % 64 != 0) return fail(KA_EINVAL, "n_replicas must be a positive multiple of 64");
     *device_bytes = state_bytes(g->N, n_replicas) + graph_device_bytes(g) +
-                    (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u;
+                    (size_t)n_replicas * 16u + (size_t)3 * n_replicas * 8u + 64u +
+                    (g->lattice ? 0 : fsat_bytes(g->N, n_replicas));
     const int wpt = ((n_replicas / 64) % 2 == 0) ? 2 : 1;
     if (ka::sweep_lds_bytes((int)g->N, wpt) + 4096 <= (size_t)ka::max_lds_bytes()) {
       // an instance on the LDS-resident path adds its pre-generated acceptance words and its
@@ -1205,6 +1219,10 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
         e = hipMemcpyAsync(s->edges, rec.data(), rec.size() * sizeof(int4), hipMemcpyHostToDevice, s->stream);
       if (e == hipSuccess)
         e = hipMemcpyAsync(s->class_start_d, cs.data(), cs.size() * sizeof(int), hipMemcpyHostToDevice, s->stream);
+      if (e == hipSuccess && fsat_bytes(s->N, s->R) > 0) {
+        e = dalloc(&s->fsat, fsat_bytes(s->N, s->R));
+        if (e == hipSuccess) e = hipMemsetAsync(s->fsat, 0, fsat_bytes(s->N, s->R), s->stream);
+      }
       if (e != hipSuccess) {
         free_device(s);
         if (s->own_stream) (void)hipStreamDestroy(s->stream);
@@ -1612,6 +1630,12 @@ extern "C" int ka_set_state(ka_sim *s, const uint64_t *n, const uint64_t *n0, co
       e = hipMemcpyAsync(dsts[k], buf.data(), words * 8, hipMemcpyHostToDevice, s->stream);
       if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
       if (e != hipSuccess) return hip_fail(e, "ka_set_state copy");
+    }
+    // the new f may have fewer bits: forget which elements were known to be full
+    if (s->fsat) {
+      e = hipMemsetAsync(s->fsat, 0, fsat_bytes(s->N, s->R), s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return hip_fail(e, "ka_set_state summary");
     }
     s->t = t;
     return KA_OK;

@@ -62,6 +62,9 @@ struct PassGraph {
   int planes;
   int blocks_per_plane;
   uint32_t t, c, key0, key1;
+  // summary of full moved-ever elements: bit plane*N + i set once every word of f at
+  // element i of plane `plane` is all ones (null: f always read where an exchange happens)
+  uint32_t *fsat;
 };
 
 // Whole sweep loop inside one workgroup per plane (plane in LDS).

@@ -64,6 +64,7 @@ struct ka_sim {
   int4 *edges = nullptr;
   int *class_start_d = nullptr;
   int32_t *site_of = nullptr;     // general graphs: canonical vertex of device index
+  uint32_t *fsat = nullptr;       // general graphs: bit per (plane, element) set once f is all ones
   ka::u64 *thr_u = nullptr;
   long long *thr_i = nullptr;
   int *err = nullptr;

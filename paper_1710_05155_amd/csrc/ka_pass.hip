@@ -61,8 +61,12 @@ __global__ __launch_bounds__(BLOCK) void k_pass_graph(PassGraph a, int m)
   const int k = blk * BLOCK + (int)threadIdx.x;
   if (k >= a.count) return;
   const size_t off = (size_t)plane * (size_t)a.N * WPT;
-  graph_edge<Z, WPT>(a.n + off, a.f + off, a.edges, a.nbr, a.stride, a.first + k, plane, m, a.t,
-                     a.c, a.key0, a.key1, a.noise);
+  if (a.fsat)
+    graph_edge<Z, WPT>(a.n + off, a.f + off, a.edges, a.nbr, a.stride, a.first + k, plane, m, a.t,
+                       a.c, a.key0, a.key1, a.noise, FSat{a.fsat, plane * a.N});
+  else
+    graph_edge<Z, WPT>(a.n + off, a.f + off, a.edges, a.nbr, a.stride, a.first + k, plane, m, a.t,
+                       a.c, a.key0, a.key1, a.noise);
 }
 
 // One launch counts a.rows states (blockIdx.z): the sim's own state, or snapshots taken by the
