@@ -244,7 +244,8 @@ typedef struct ka_batch ka_batch;
  * stream the library creates).  Members' own streams are ordered before their batch work. */
 int ka_batch_create(int capacity, void *hip_stream, ka_batch **out);
 
-/* Add sim s to advance by n_sweeps sweeps, starting at the next step enqueued.  The sim
+/* Add sim s to advance by n_sweeps sweeps, starting at the next step enqueued (or later,
+ * under KA_BOPT_CACHE_BUDGET).  The sim
  * must be on the batch's device and in no other batch; until it is detached (ka_batch_poll,
  * ka_batch_wait_all) every other call on it returns KA_ESTATE.  *slot receives its slot. */
 int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot);
@@ -266,10 +267,18 @@ int ka_batch_wait_all(ka_batch *b);
 
 /* Options: KA_BOPT_AUTOTUNE (1 default / 0), KA_BOPT_BLOCK (tile = workgroup size: 128,
  * 256 or 512; disables autotuning), KA_BOPT_GRAPH_STEPS (steps per captured graph, default
- * 64; 0 = plain launches). */
+ * 64; 0 = plain launches), KA_BOPT_CACHE_BUDGET (bytes, default 0 = off; set before the
+ * first ka_batch_add): members whose working set (n and f, 2 x 8 x N x n_replicas/64 bytes)
+ * is at least 1/8 of the budget are large, and a large member starts only while it fits
+ * the budget next to the large members still running (or when none runs); otherwise it
+ * waits, in the order added, and starts at the step where enough of them have finished.
+ * Sized to the device's last-level cache (256 MiB Infinity Cache on MI355X), this keeps the
+ * large members' state cache-resident between steps.  A member's result does not depend
+ * on when it starts; ka_batch_steps_left counts the waiting members' steps too. */
 #define KA_BOPT_AUTOTUNE 1
 #define KA_BOPT_BLOCK 2
 #define KA_BOPT_GRAPH_STEPS 4
+#define KA_BOPT_CACHE_BUDGET 5
 int ka_batch_set_option(ka_batch *b, int option, int64_t value);
 
 /* Global step (enqueued), attached members, tile size in use, and tiles per step of the

@@ -66,6 +66,17 @@ __device__ __forceinline__ void run_graph_tile(const BatchMember &mb, int local,
   const size_t off = (size_t)plane * (size_t)mb.N * WPT;
   u64 *n = mb.n + off, *f = mb.f + off;
   const size_t st = (size_t)mb.stride;
+  if (mb.fsat) {
+    const FSat sat{mb.fsat, plane * mb.N};
+    switch (mb.z) {
+      case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      case 5: graph_edge<5, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      case 6: graph_edge<6, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      default: break;
+    }
+    return;
+  }
   switch (mb.z) {
     case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
     case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;

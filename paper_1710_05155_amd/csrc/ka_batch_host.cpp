@@ -79,6 +79,14 @@ struct ka_batch {
   std::vector<ka_sim *> sims;            // per slot (nullptr = free)
   std::vector<int64_t> sweeps;           // per slot
   std::vector<std::vector<int>> class_sizes;  // per slot, graphs only
+  // Infinity-Cache-aware admission (KA_BOPT_CACHE_BUDGET): members whose working set (n and
+  // f) is at least budget/8 are "large"; a large member starts only while the large members
+  // running with it fit the budget, otherwise it waits (FIFO) and starts at the step where
+  // enough of them have finished.
+  int64_t cache_budget = 0;
+  std::vector<int64_t> ws;               // per slot: bytes of n and f
+  std::vector<char> waiting_flag;        // per slot: added but not started yet
+  std::deque<int> waiting;               // slots in admission order
   int n_members = 0;                     // highest used slot + 1
   int64_t step = 0;                      // steps enqueued
   int64_t done_step = 0;                 // steps known complete on the device
@@ -131,6 +139,79 @@ int tiles_per_plane(const ka_batch *b, int k, int block)
 bool active_at(const ka_batch *b, int k, int64_t s)
 {
   return b->sims[(size_t)k] && b->tab[(size_t)k].s_begin <= s && s < b->tab[(size_t)k].s_end;
+}
+
+bool large_member(const ka_batch *b, int k)
+{
+  return b->cache_budget > 0 && b->ws[(size_t)k] * 8 >= b->cache_budget;
+}
+
+// Bytes of large started members that still run at or after step s.
+int64_t large_bytes_from(const ka_batch *b, int64_t s)
+{
+  int64_t bytes = 0;
+  for (int k = 0; k < b->n_members; ++k)
+    if (b->sims[(size_t)k] && !b->waiting_flag[(size_t)k] && large_member(b, k) && b->tab[(size_t)k].s_end > s)
+      bytes += b->ws[(size_t)k];
+  return bytes;
+}
+
+// Whether a waiting large member of ws bytes may start at step s next to `running` bytes of
+// large members (always, when none runs).
+bool fits_budget(const ka_batch *b, int64_t running, int64_t ws)
+{
+  return running == 0 || running + ws <= b->cache_budget;
+}
+
+void start_member(ka_batch *b, int k, int64_t s)
+{
+  ka::BatchMember &m = b->tab[(size_t)k];
+  m.s_begin = s;
+  m.s_end = s + (int64_t)m.C * b->sweeps[(size_t)k];
+  b->waiting_flag[(size_t)k] = 0;
+  b->dirty = true;
+}
+
+// Start waiting members, in order, that fit next to the large members running at the
+// current step.
+void admit_waiting(ka_batch *b)
+{
+  while (!b->waiting.empty()) {
+    const int k = b->waiting.front();
+    if (!fits_budget(b, large_bytes_from(b, b->step), b->ws[(size_t)k])) break;
+    b->waiting.pop_front();
+    start_member(b, k, b->step);
+  }
+}
+
+// Step at which every member, waiting ones included, will have finished: the admissions of
+// admit_waiting replayed on the host.
+int64_t projected_end(const ka_batch *b)
+{
+  int64_t end = b->step;
+  std::vector<std::pair<int64_t, int64_t>> large;   // (end step, bytes) of started large members
+  for (int k = 0; k < b->n_members; ++k) {
+    if (!b->sims[(size_t)k] || b->waiting_flag[(size_t)k]) continue;
+    end = std::max<int64_t>(end, b->tab[(size_t)k].s_end);
+    if (large_member(b, k) && b->tab[(size_t)k].s_end > b->step) large.emplace_back(b->tab[(size_t)k].s_end, b->ws[(size_t)k]);
+  }
+  int64_t s = b->step;
+  for (int k : b->waiting) {
+    for (;;) {
+      int64_t running = 0, next = INT64_MAX;
+      for (const auto &e : large)
+        if (e.first > s) {
+          running += e.second;
+          next = std::min(next, e.first);
+        }
+      if (fits_budget(b, running, b->ws[(size_t)k])) break;
+      s = next;
+    }
+    const int64_t e = s + (int64_t)b->tab[(size_t)k].C * b->sweeps[(size_t)k];
+    large.emplace_back(e, b->ws[(size_t)k]);
+    end = std::max(end, e);
+  }
+  return end;
 }
 
 void drop_graph(ka_batch::Graph &g)
@@ -242,6 +323,7 @@ hipError_t enqueue_steps(ka_batch *b, int64_t n)
   hipError_t e = hipSuccess;
   while (n > 0 && e == hipSuccess) {
     if (!b->seg_valid || b->dirty || b->step >= b->seg_end) {
+      admit_waiting(b);
       e = new_segment(b);
       if (e != hipSuccess) break;
     }
@@ -367,6 +449,8 @@ extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
     b->sims.assign((size_t)capacity, nullptr);
     b->sweeps.assign((size_t)capacity, 0);
     b->class_sizes.assign((size_t)capacity, std::vector<int>());
+    b->ws.assign((size_t)capacity, 0);
+    b->waiting_flag.assign((size_t)capacity, 0);
     hipError_t e = hipSuccess;
     if (hip_stream) {
       b->stream = (hipStream_t)hip_stream;
@@ -430,6 +514,7 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
     m.nbr = s->nbr;
     m.stride = (long long)s->edges_total;
     m.class_start = s->class_start_d;
+    m.fsat = s->fsat;
     m.kind = s->lattice ? 0 : 1;
     m.d = s->geom.d;
     m.L = s->geom.L;
@@ -446,15 +531,24 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
     m.key1 = (uint32_t)(s->seed >> 32);
     m.noise = s->noise;
     m.t0 = (uint32_t)s->t;
-    m.s_begin = b->step;
-    m.s_end = b->step + (int64_t)s->C * n_sweeps;
     b->class_sizes[(size_t)k].clear();
     if (!s->lattice)
       for (int c = 0; c < s->C; ++c) b->class_sizes[(size_t)k].push_back(s->plan->class_start[(size_t)c + 1] - s->plan->class_start[(size_t)c]);
     b->tab[(size_t)k] = m;
     b->sims[(size_t)k] = s;
     b->sweeps[(size_t)k] = n_sweeps;
+    b->ws[(size_t)k] = (int64_t)2 * s->N * s->W * 8;
     b->n_members = std::max(b->n_members, k + 1);
+    if (large_member(b, k) && (!b->waiting.empty() || !fits_budget(b, large_bytes_from(b, b->step), b->ws[(size_t)k]))) {
+      // waits until enough of the large members already running have finished
+      b->tab[(size_t)k].s_begin = INT64_MAX;
+      b->tab[(size_t)k].s_end = INT64_MAX;
+      b->waiting_flag[(size_t)k] = 1;
+      b->waiting.push_back(k);
+    } else {
+      b->waiting_flag[(size_t)k] = 0;
+      start_member(b, k, b->step);
+    }
     b->dirty = true;
     s->batch = b;
     if (slot) *slot = k;
@@ -480,10 +574,7 @@ extern "C" int ka_batch_steps_left(const ka_batch *b, int64_t *steps_left)
 {
   return ka_guard([&]() -> int {
     if (!b || !steps_left) return bfail(KA_EINVAL, "NULL argument");
-    int64_t left = 0;
-    for (int k = 0; k < b->n_members; ++k)
-      if (b->sims[(size_t)k]) left = std::max<int64_t>(left, b->tab[(size_t)k].s_end - b->step);
-    *steps_left = left;
+    *steps_left = projected_end(b) - b->step;
     return KA_OK;
   });
 }
@@ -543,6 +634,13 @@ extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
       case KA_BOPT_GRAPH_STEPS:
         if (value < 0 || value > 4096) return bfail(KA_EINVAL, "graph steps must be in [0, 4096]");
         b->graph_steps = (int)value;
+        return KA_OK;
+      case KA_BOPT_CACHE_BUDGET:
+        if (value < 0) return bfail(KA_EINVAL, "cache budget must be >= 0");
+        if (!b->waiting.empty() || b->n_members > 0)
+          for (int k = 0; k < b->n_members; ++k)
+            if (b->sims[(size_t)k]) return bfail(KA_ESTATE, "the cache budget is set before members are added");
+        b->cache_budget = value;
         return KA_OK;
       default:
         return bfail(KA_EINVAL, "unknown batch option %d", option);

@@ -213,6 +213,7 @@ struct BatchMember {
   uint32_t t0;
   int tiles_per_plane;         // tiles of BLOCK threads per plane (graphs: largest class)
   long long s_begin, s_end;
+  uint32_t *fsat;              // graphs: summary of full moved-ever elements (PassGraph::fsat)
 };
 
 // Work list of one segment (steps between membership changes): tile q belongs to member

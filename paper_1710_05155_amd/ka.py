@@ -55,6 +55,7 @@ class JobDesc(ctypes.Structure):
 KA_BOPT_AUTOTUNE = 1
 KA_BOPT_BLOCK = 2
 KA_BOPT_GRAPH_STEPS = 4
+KA_BOPT_CACHE_BUDGET = 5
 
 
 class KaError(RuntimeError):

@@ -231,3 +231,76 @@ def test_batch_shared_noise_members_equal_solo(graphs):
     states = [ka.ka_get_state(s) for s in sims]
     b.free()
     _assert_same(states, ref)
+
+
+BUDGET_MEMBERS = [
+    # large (working set 64 KiB: 2D L=64, 64 replicas, C=8) and small members
+    ("lat", (2, 64), 4, 2, 0.7, 64, 40, 5),
+    ("lat", (2, 64), 4, 1, 0.6, 64, 41, 5),
+    ("rrg", 2000, 4, 2, 0.65, 64, 42, 3),
+    ("lat", (2, 64), 4, 3, 0.8, 64, 43, 5),
+    ("lat", (2, 8), 4, 2, 0.6, 64, 44, 7),
+    ("lat", (2, 64), 4, 2, 0.5, 64, 45, 5),
+]
+
+
+# Steps under each budget, worked out by hand from the admission rule: large members are
+# the 2D L=64 ones (64 KiB, 40 steps) and, below 250 KiB, the graph (31.25 KiB, 15 classes x
+# 3 sweeps = 45 steps); the small 2D L=8 member takes 56 steps from the start.
+#   128 KiB: two L=64 to step 40, then graph + L=64 (to 85 / 80), then the last L=64 from 80 to 120.
+#   192 KiB: two L=64 + graph at once; at 40 the other two L=64 start, to 80.
+#    64 KiB: one large member at a time: 40, 80, 125 (graph), 165, 205.
+#     1 MiB: nothing is large; the small member's 56 steps set the length.
+@pytest.mark.parametrize("budget,expected_steps", [(1 << 17, 120), (3 << 16, 80), (1 << 16, 205), (1 << 20, 56)])
+def test_cache_budget_members_equal_solo(budget, expected_steps):
+    """Infinity-Cache-aware admission (KA_BOPT_CACHE_BUDGET): members whose working set is
+    at least 1/8 of the budget start only while they fit it next to the large members still
+    running, in the order added.  ka_batch_steps_left projects those admissions exactly, so
+    running that many steps completes every member, and each ends in its solo state."""
+    import time
+    _say(f"batch: cache budget {budget}")
+    graphs = [_graph(spec) for spec in BUDGET_MEMBERS]
+    solo = []
+    for spec, g in zip(BUDGET_MEMBERS, graphs):
+        s = _make(spec, g)
+        ka.ka_sweep(s, spec[7])
+        solo.append(ka.ka_get_state(s))
+        s.free()
+    b = ka.ka_batch_create(16)
+    ka.ka_batch_set_option(b, ka.KA_BOPT_CACHE_BUDGET, budget)
+    sims = []
+    for spec, g in zip(BUDGET_MEMBERS, graphs):
+        s = _make(spec, g)
+        ka.ka_batch_add(b, s, spec[7])
+        sims.append(s)
+    assert graphs[2].C * 3 == 45
+    left = ka.ka_batch_steps_left(b)
+    assert left == expected_steps
+    ka.ka_batch_run(b, left)
+    assert ka.ka_batch_steps_left(b) == 0
+    done = set()
+    deadline = time.time() + 60
+    while len(done) < len(BUDGET_MEMBERS):
+        assert time.time() < deadline, "members did not complete in the projected steps"
+        done.update(ka.ka_batch_poll(b))
+        time.sleep(0.001)
+    for k, (s, ref) in enumerate(zip(sims, solo)):
+        for x, y in zip(ka.ka_get_state(s), ref):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), k
+    b.free()
+    for s in sims:
+        s.free()
+
+
+def test_cache_budget_set_before_members(graphs):
+    b = ka.ka_batch_create(4)
+    s = _make(MEMBERS[0], graphs[0])
+    ka.ka_batch_add(b, s, 1)
+    with pytest.raises(ka.KaError) as e:
+        ka.ka_batch_set_option(b, ka.KA_BOPT_CACHE_BUDGET, 1 << 20)
+    assert e.value.code == ka.KA_ESTATE
+    with pytest.raises(ka.KaError) as e:
+        ka.ka_batch_set_option(b, ka.KA_BOPT_CACHE_BUDGET, -1)
+    assert e.value.code == ka.KA_EINVAL
+    b.free()
+    s.free()
