@@ -19,6 +19,11 @@ separate launches on two streams that overlap, and this figure is each launch's 
 wall time (the launches' own durations overlap and are longer).  Last, the oracle's rate on
 a bounded sample on this host's cores.
 
+After the headline (default workload only), the batched form (256 uneven instances) and the
+continuous-batching server (a Poisson trace, --jobs jobs at --rate per second and at half the
+measured capacity) are measured against one job at a time and added as "batch256" and
+"serve"; --no-extras skips them.
+
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload cubic128]
 """
 import argparse
@@ -149,14 +154,13 @@ def graph_bytes_model(adj, eu, ev, ec, C, z, W):
     return total
 
 
-def run_batch_workload(args):
-    """256 uneven instances advanced together by the batched step kernel, against the same
-    jobs run one at a time with the single-instance path."""
-    import numpy as np
+def batch_measure(steps, warmup, sweeps=1000, serial=True):
+    """256 uneven instances advanced together by the batched step kernel (timed `steps`
+    times after `warmup` untimed runs), against the same jobs run one at a time with the
+    single-instance path (once).  Returns a dict."""
     import torch
     from paper_1710_05155_amd import ka, workloads
 
-    sweeps = args.sweeps or 1000
     man = workloads.batch_manifest(256, sweeps=sweeps)
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
@@ -169,18 +173,17 @@ def run_batch_workload(args):
             continue
         if inst["kind"] == "lattice":
             graphs[key] = ka.ka_graph_lattice(inst["d"], inst["L"])
-            bytes_per_sweep[key] = 16 * inst["N"] * (inst["R"] // 64) * 4 * inst["d"]
+            bytes_per_sweep[key] = 12 * inst["N"] * (inst["R"] // 64) * 4 * inst["d"]
         else:
             g = ka.ka_graph_rrg(inst["N"], inst["z"], inst["graph_seed"])
             graphs[key] = g
             adj, eu, ev, ec = ka.ka_graph_export(g)
             bytes_per_sweep[key] = graph_bytes_model(adj, eu, ev, ec, g.C, g.z, inst["R"] // 64)
-    log(f"built {len(graphs)} graphs in {time.perf_counter() - t0:.1f} s")
+    log(f"batch: built {len(graphs)} graphs in {time.perf_counter() - t0:.1f} s")
     attempts = sum(graphs[i["key"]].N * i["R"] * i["sweeps"] for i in man)
     model_bytes = sum(bytes_per_sweep[i["key"]] * i["sweeps"] for i in man)
 
     shape = {}
-
     # The members' initial states are built on a few streams of their own, so that the
     # one-workgroup-per-replica-pair init kernels of different members run side by side;
     # ka_batch_add orders each member's init before the batch's steps.
@@ -213,7 +216,7 @@ def run_batch_workload(args):
             timed_kernel.append((e0.elapsed_time(e1), steps))
         return steps
 
-    def serial():
+    def one_at_a_time():
         for i in man:
             s = ka.ka_init(graphs[i["key"]], i["m"], i["rho"], i["seed"], i["R"], stream=stream)
             ka.ka_sweep(s, i["sweeps"])
@@ -221,57 +224,71 @@ def run_batch_workload(args):
             assert (dens == s.K).all()
             s.free()
 
-    for k in range(args.warmup):
+    for k in range(warmup):
         t = time.perf_counter()
         batched(None)
-        log(f"warmup {k}: {time.perf_counter() - t:.2f} s, tuned shape {shape}")
+        log(f"batch warmup {k}: {time.perf_counter() - t:.2f} s, tuned shape {shape}")
     kern = []
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for k in range(args.steps):
-        steps = batched(kern)
-        log(f"step {k}: step kernels {steps}, {kern[-1][0]:.1f} ms of them")
+    for k in range(steps):
+        n_steps = batched(kern)
+        log(f"batch step {k}: step kernels {n_steps}, {kern[-1][0]:.1f} ms of them")
     torch.cuda.synchronize()
     wall = time.perf_counter() - t
-    result = {
-        "metric": "site-replica move attempts/s (1 GPU)",
-        "value": attempts * args.steps / wall,
-        "unit": "site-replica move attempts/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": wall * 1000.0 / args.steps,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "256 uneven instances (2D L 32-512, 3D L 16-128, RRG N 2^12-2^18 z 3-5, "
-                               f"m 1..z-1, rho U[0.5,0.9], 64 replicas), {sweeps} sweeps each, batched "
-                               "step kernel in captured graphs, autotuned launch shape",
-                   "instances": len(man), "sites_total": int(sum(graphs[i["key"]].N for i in man)),
-                   "launch_shape": shape},
-    }
     ms = sum(k[0] for k in kern)
     launches = sum(k[1] for k in kern)
-    achieved = model_bytes * args.steps / (ms / 1000.0) / 1e9
-    result["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                          "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch_step",
-                          "avg_launch_us": ms * 1000.0 / launches, "bytes_per_launch": model_bytes / (launches / args.steps)}
-    if not args.no_serial:
-        log("serial one-at-a-time baseline ...")
+    achieved = model_bytes * steps / (ms / 1000.0) / 1e9
+    out = {"value": attempts * steps / wall, "unit": "site-replica move attempts/s",
+           "ms_per_batch": wall * 1000.0 / steps, "instances": len(man), "sweeps_each": sweeps,
+           "sites_total": int(sum(graphs[i["key"]].N for i in man)), "launch_shape": dict(shape),
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch_step",
+                        "avg_launch_us": ms * 1000.0 / launches,
+                        "bytes_per_launch": model_bytes / (launches / steps),
+                        "byte_model": "12 B per site-word per lattice class pass; graph members as bench.graph_bytes_model"}}
+    if serial:
+        log("batch: one-at-a-time baseline ...")
         torch.cuda.synchronize()
         t = time.perf_counter()
-        serial()
+        one_at_a_time()
         torch.cuda.synchronize()
         ws = time.perf_counter() - t
-        result["serial_one_at_a_time"] = {"value": attempts / ws, "ms": ws * 1000.0}
-        result["speedup_vs_serial"] = ws / (wall / args.steps)
+        out["one_at_a_time"] = {"value": attempts / ws, "ms": ws * 1000.0}
+        out["speedup_vs_one_at_a_time"] = ws / (wall / steps)
+    return out
+
+
+def run_batch_workload(args):
+    """The batched workload as the bench line."""
+    r = batch_measure(args.steps, args.warmup, sweeps=args.sweeps or 1000, serial=not args.no_serial)
+    result = {
+        "metric": "site-replica move attempts/s (1 GPU)",
+        "value": r["value"],
+        "unit": "site-replica move attempts/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["ms_per_batch"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "256 uneven instances (2D L 32-512, 3D L 16-128, RRG N 2^12-2^18 z 3-5, "
+                               f"m 1..z-1, rho U[0.5,0.9], 64 replicas), {r['sweeps_each']} sweeps each, batched "
+                               "step kernel in captured graphs, autotuned launch shape",
+                   "instances": r["instances"], "sites_total": r["sites_total"], "launch_shape": r["launch_shape"]},
+        "roofline": r["roofline"],
+    }
+    for k in ("one_at_a_time", "speedup_vs_one_at_a_time"):
+        if k in r:
+            result[k] = r[k]
     print(json.dumps(result), flush=True)
 
 
-def run_serve_workload(args):
-    """Continuous-batching job server on Poisson arrivals vs serial per-job launches."""
+def serve_measure(n_jobs, rate_per_s, serial=True):
+    """Continuous-batching job server on a Poisson trace of n_jobs jobs at the stated rate and
+    at half of the measured capacity, each against serial per-job launches.  Returns a dict."""
     import numpy as np
     import torch
     from paper_1710_05155_amd import ka, workloads
 
     torch.cuda.set_device(0)
-    n_jobs = args.jobs
     t0 = time.perf_counter()
     graphs = {}
 
@@ -294,8 +311,8 @@ def run_serve_workload(args):
                 j["obs"].append(j["sweeps"])
         return jobs
 
-    base = trace(args.rate)
-    log(f"built {len(graphs)} graphs in {time.perf_counter() - t0:.1f} s")
+    base = trace(rate_per_s)
+    log(f"serve: built {len(graphs)} graphs in {time.perf_counter() - t0:.1f} s")
     work = [j["graph"].N * j["R"] * j["sweeps"] for j in base]
     mean_work = float(np.mean(work))
 
@@ -322,7 +339,7 @@ def run_serve_workload(args):
         sv.free()
         return end - start, np.array(lat), stats
 
-    def serial(jobs):
+    def serial_run(jobs):
         stream = torch.cuda.Stream()
         start = time.perf_counter()
         lat = []
@@ -340,12 +357,12 @@ def run_serve_workload(args):
         return float(np.percentile(a, q))
 
     out = {}
-    rates = [("stated", args.rate)]
+    rates = [("stated", rate_per_s)]
     # a warm-up pass at the stated rate measures capacity for the half-load rate
     wall, lat, stats = served(base)
     capacity = stats["attempts"] / wall
     rates.append(("half_capacity", 0.5 * capacity / mean_work))
-    log(f"capacity estimate {capacity:.3e} attempts/s -> half-load rate {rates[1][1]:.2f} jobs/s")
+    log(f"serve: capacity estimate {capacity:.3e} attempts/s -> half-load rate {rates[1][1]:.2f} jobs/s")
     for name, rate in rates:
         jobs = trace(rate)
         total = float(sum(j["graph"].N * j["R"] * j["sweeps"] for j in jobs))
@@ -354,24 +371,30 @@ def run_serve_workload(args):
                  "throughput": total / wall, "makespan_s": wall, "p50_latency_s": pct(lat, 50),
                  "p99_latency_s": pct(lat, 99), "peak_active": stats["peak_active"]}
         log(f"served {name}: {entry}")
-        if not args.no_serial:
-            sw, slat = serial(jobs)
+        if serial:
+            sw, slat = serial_run(jobs)
             entry["serial"] = {"throughput": total / sw, "makespan_s": sw, "p50_latency_s": pct(slat, 50),
                                "p99_latency_s": pct(slat, 99)}
             log(f"serial {name}: {entry['serial']}")
         out[name] = entry
-    main_entry = out["stated"]
+    return {"jobs": n_jobs, "capacity_attempts_per_s": capacity, "rates": out}
+
+
+def run_serve_workload(args):
+    r = serve_measure(args.jobs, args.rate, serial=not args.no_serial)
+    main_entry = r["rates"]["stated"]
     result = {
         "metric": "site-replica move attempts/s (1 GPU); p50/p99 job latency served",
         "value": main_entry["throughput"],
         "unit": "site-replica move attempts/s",
         "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": main_entry["makespan_s"] * 1000.0,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": f"{n_jobs} Poisson-arriving jobs (rate {args.rate}/s, seed 5) from the 256-instance "
+        "config": {"workload": f"{args.jobs} Poisson-arriving jobs (rate {args.rate}/s, seed 5) from the 256-instance "
                                "size mix, sweeps log-uniform in [10^2, 10^4], observations on a log grid, "
                                "continuous batching with admission by device footprint",
-                   "jobs": n_jobs},
-        "serving": out,
+                   "jobs": args.jobs},
+        "serving": r["rates"],
+        "capacity_attempts_per_s": r["capacity_attempts_per_s"],
     }
     print(json.dumps(result), flush=True)
 
@@ -398,6 +421,8 @@ def main():
                     help="lattice workloads: run the word planes on two streams of each sim's own "
                          "(KA_OPT_PLANE_STREAMS=1) instead of one launch per class pass")
     ap.add_argument("--no-serial", action="store_true", help="batch workload: skip the one-at-a-time baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="cubic128: skip the batch256 and serve figures after the headline")
     ap.add_argument("--replicas", type=int, default=None, help="override the replica count (exploration only)")
     ap.add_argument("--jobs", type=int, default=200, help="serve workload: jobs in the trace")
     ap.add_argument("--rate", type=float, default=200.0, help="serve workload: mean arrivals per second")
@@ -619,6 +644,31 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w)
+    if args.workload == "cubic128" and not args.no_extras and args.sweeps is None and args.replicas is None:
+        # After the headline's timed region: the batched and served forms against one job at a
+        # time on the same GPU (their own workloads: --workload batch256 / serve).
+        log("extra: batch of 256 uneven instances ...")
+        b = batch_measure(1, 1)
+        result["batch256"] = {
+            "value": b["value"], "unit": b["unit"], "ms_per_batch": b["ms_per_batch"],
+            "one_at_a_time_value": b["one_at_a_time"]["value"], "one_at_a_time_ms": b["one_at_a_time"]["ms"],
+            "speedup_vs_one_at_a_time": b["speedup_vs_one_at_a_time"], "launch_shape": b["launch_shape"],
+            "config": "256 uneven instances (2D L 32-512, 3D L 16-128, RRG N 2^12-2^18 z 3-5), 64 replicas, "
+                      "1000 sweeps each; 1 warm-up batch, 1 timed"}
+        log(f"extra: serving trace of {args.jobs} jobs ...")
+        sv = serve_measure(args.jobs, args.rate)
+        result["serve"] = {
+            name: {"rate_jobs_per_s": e["rate_jobs_per_s"], "throughput": e["throughput"],
+                   "p50_latency_s": e["p50_latency_s"], "p99_latency_s": e["p99_latency_s"],
+                   "serial_throughput": e["serial"]["throughput"],
+                   "serial_p50_latency_s": e["serial"]["p50_latency_s"],
+                   "serial_p99_latency_s": e["serial"]["p99_latency_s"]}
+            for name, e in sv["rates"].items()}
+        result["serve"]["jobs"] = sv["jobs"]
+        result["serve"]["capacity_attempts_per_s"] = sv["capacity_attempts_per_s"]
+        result["serve"]["config"] = (f"{args.jobs} Poisson-arriving jobs (seed 5) from the 256-instance mix, "
+                                     "sweeps log-uniform in [10^2, 10^4], at the stated rate and at half the "
+                                     "measured capacity")
     print(json.dumps(result), flush=True)
 
 

@@ -626,6 +626,12 @@ bool plane_split(ka_sim *s)
 
 // One class pass over global memory: one launch over all planes on the sim's stream, or
 // with `split` one launch per plane on the plane streams.
+// Rows per tile (log2) of the large-3D-lattice chunk order in the class pass.
+#ifndef KA_ROW_TILE_LOG2
+#define KA_ROW_TILE_LOG2 5
+#endif
+constexpr int kRowTileLog2 = KA_ROW_TILE_LOG2;
+
 hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
 {
   const uint32_t k0 = (uint32_t)s->seed, k1 = (uint32_t)(s->seed >> 32);
@@ -652,6 +658,16 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
     a.key0 = k0;
     a.key1 = k1;
     a.noise = s->noise;
+    // Large 3D lattices (Q = L/4 a power of two >= 64): rows visited in tiles of 32 along
+    // p1, so that the +-e_2 neighbour rows of a chunk are read within one L2's reach
+    a.row_tile_log2 = 0;
+    a.q_log2 = 0;
+    if (s->geom.d == 3 && s->geom.Q >= 64 && (s->geom.Q & (s->geom.Q - 1)) == 0) {
+      int lq = 0;
+      while ((1 << lq) < s->geom.Q) ++lq;
+      a.q_log2 = lq;
+      a.row_tile_log2 = kRowTileLog2;
+    }
     if (split) {
       err = hipSuccess;
       for (int p = 0; p < s->planes && err == hipSuccess; ++p) {

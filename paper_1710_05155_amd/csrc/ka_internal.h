@@ -47,6 +47,10 @@ struct PassLattice {
   int plane0;                // first plane of this launch
   int blocks_per_plane;
   uint32_t t, c, key0, key1;
+  // 3D, Q a power of two >= 64: chunks visited in tiles of 2^row_tile_log2 rows (0 = in
+  // order); q_log2 = log2(Q)
+  int row_tile_log2;
+  int q_log2;
 };
 
 struct PassGraph {

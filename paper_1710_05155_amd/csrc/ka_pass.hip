@@ -44,7 +44,19 @@ __global__ __launch_bounds__(kPassBlock) void k_pass_lattice(PassLattice a, int 
   // Waves are 64-thread aligned and span is a multiple of 64, so q is the same on every lane
   // of the wave: take it (and the sublattice) in scalar registers.
   const int q = __builtin_amdgcn_readfirstlane(rem >> 6);
-  const int pos = chunk * 64 + (rem & 63);
+  int chk = chunk;
+  if (D == 3 && a.row_tile_log2 > 0) {
+    // Rows (p1, p2) of whole chunks visited in tiles of T = 2^row_tile_log2 rows along p1,
+    // p2 next: the +-e_2 neighbour rows are then T rows apart instead of Q (inside one L2),
+    // at the cost of the +-e_1 neighbours at tile edges.  A permutation of the chunks.
+    const int lt = a.row_tile_log2, lq = a.q_log2, lr = lq - 6;
+    const int row = chk >> lr, xc = chk & ((1 << lr) - 1);
+    const int tb = row >> (lt + lq);
+    const int in = row & ((1 << (lt + lq)) - 1);
+    const int p2 = in >> lt, p1 = (tb << lt) | (in & ((1 << lt) - 1));
+    chk = ((p1 | (p2 << lq)) << lr) | xc;
+  }
+  const int pos = chk * 64 + (rem & 63);
   if (pos >= a.g.P) return;
   const int sub = class_sublattice(D, MU, (int)(a.c & 3u), q);
   const size_t off = (size_t)plane * (size_t)a.g.N * WPT;

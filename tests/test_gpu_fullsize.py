@@ -116,3 +116,29 @@ def test_rrg20_graph_and_sampled_replicas(oracle):
         d2, o2, p2 = ka.ka_run(sim, grid)
         _check_invariants(K, np.vstack([dens, d2]), np.vstack([ov, o2]), np.vstack([pers, p2]))
         sim.free()
+
+
+@pytest.mark.parametrize("R", [256, 64])
+def test_cubic256_tiled_order_sampled_replicas(oracle, R):
+    """3D L=256 (Q = 64): the class pass visits chunk rows in tiles along p1 (a permutation
+    of the edges of a class, which commute).  Replicas 0 and R-1 match the oracle bit for bit
+    after 2 sweeps, with word pairs (256 replicas) and single words (64)."""
+    g = ka.ka_graph_lattice(3, 256)
+    og = oracle.lattice(3, 256)
+    K = oracle.k_from_rho(og.N, 0.85)
+    _say(f"cubic256 R={R}: 2 sweeps, replicas 0 and {R - 1}")
+    sim = ka.ka_init(g, 3, 0.85, 7, R)
+    assert ka.ka_sim_path(sim) == 1
+    dens, ov, pers = ka.ka_run(sim, [1, 2])
+    n, n0, f, t = ka.ka_get_state(sim)
+    sim.free()
+    reps = [0, R - 1]
+    orc = oracle.Sim(og, 3, K, 7, reps)
+    for q, tt in enumerate([1, 2]):
+        orc.sweep(tt - orc.t)
+        od, oo, op = orc.observe()
+        for k, b in enumerate(reps):
+            assert (dens[q, b], ov[q, b], pers[q, b]) == (od[k], oo[k], op[k]), (tt, b)
+    for k, b in enumerate(reps):
+        assert np.array_equal(_replica_bits(n, b), orc.occ[k]), b
+        assert np.array_equal(_replica_bits(f, b), orc.moved[k]), b
