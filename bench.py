@@ -328,6 +328,14 @@ def serve_measure(n_jobs, rate_per_s, serial=True):
                 time.sleep(dt)
             ids.append(ka.ka_server_submit(sv, j["graph"], j["m"], j["rho"], j["seed"], j["R"], j["sweeps"],
                                            obs_times=j["obs"]))
+            if len(ids) % 500 == 0:
+                log(f"serve: {len(ids)}/{len(jobs)} jobs submitted at {time.perf_counter() - start:.1f} s")
+        while True:
+            done = ka.ka_server_stats(sv)["jobs_done"]
+            if done >= len(ids):
+                break
+            log(f"serve: {done}/{len(ids)} jobs done at {time.perf_counter() - start:.1f} s")
+            time.sleep(min(30.0, max(0.05, 0.25 * (time.perf_counter() - start))))
         ka.ka_server_wait_idle(sv)
         end = time.perf_counter()
         lat = []
@@ -351,6 +359,8 @@ def serve_measure(n_jobs, rate_per_s, serial=True):
             ka.ka_run(s, j["obs"])
             s.free()
             lat.append(time.perf_counter() - start - j["arrival_s"])
+            if len(lat) % 250 == 0:
+                log(f"serve: serial {len(lat)}/{len(jobs)} jobs done at {time.perf_counter() - start:.1f} s")
         return time.perf_counter() - start, np.array(lat)
 
     def pct(a, q):
