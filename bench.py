@@ -129,7 +129,8 @@ def cpu_baseline(w, seconds_target=15.0):
     total_sweeps = n + 1
     rate = g.N * len(reps) * total_sweeps / (dt + one)
     return {"value": rate, "unit": "site-replica move attempts/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(reps)} replicas x {total_sweeps} sweeps of the same lattice at rho={rho} "
+            "sample": f"{len(reps)} replicas x {total_sweeps} sweeps of the same "
+                      f"{'lattice' if w['kind'] == 'lattice' else 'graph'} at rho={rho} "
                       f"(one replica per thread), sweeps only"}
 
 
@@ -152,6 +153,57 @@ def graph_bytes_model(adj, eu, ev, ec, C, z, W):
         touched[adj[ev[sel]].ravel()] = True
         total += int(touched.sum()) * 8 * W + Ec * (16 + 2 * 4 * (z - 1) + 2 * 8 * W + 2 * 8 * W)
     return total
+
+
+def hbm_regime_measure(stream, jobs=2):
+    """3D L=256 x 256 replicas, rho = 0.85, 200 sweeps per job with the 38-point log grid cut at
+    200 (state 3 x 512 MiB, beyond the 256 MiB Infinity Cache): rate and the class pass's
+    roofline under the 12 B model, timed like the headline (HIP events around each job's
+    sweep loop, less the observations timed on their own)."""
+    import torch
+    from paper_1710_05155_amd import ka
+    w = WORKLOADS["cubic256"]
+    g = ka.ka_graph_lattice(w["d"], w["L"])
+    grid = obs_grid(w)
+    run_ms = []
+    launches = 0
+    for k in range(jobs + 1):
+        sim = ka.ka_init(g, w["m"], w["rhos"][0], 1, w["R"], stream=stream)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dens, _, _ = ka.ka_run(sim, grid)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        assert (dens == sim.K).all()
+        if k > 0:    # the first job is a warm-up
+            run_ms.append(e0.elapsed_time(e1))
+            launches += ka.ka_timing(sim)[0]
+        sim.free()
+    sim = ka.ka_init(g, w["m"], w["rhos"][0], 1, w["R"], stream=stream)
+    torch.cuda.synchronize()
+    oa, ob = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    oa.record(stream)
+    ka.ka_run(sim, [0] * len(grid))
+    ob.record(stream)
+    torch.cuda.synchronize()
+    obs_ms = oa.elapsed_time(ob)
+    sim.free()
+    N, W = g.N, w["R"] // 64
+    sweep_ms = sum(run_ms) - jobs * obs_ms
+    avg_s = sweep_ms / launches / 1000.0
+    B = class_pass_bytes(w, N, W)
+    B16 = class_pass_bytes(w, N, W, with_moved_ever=True)
+    srcs = [os.path.join(ROOT, "paper_1710_05155_amd", "csrc", f) for f in ("ka_device.h", "ka_pass.hip")]
+    cfile = os.path.join(ROOT, "profiles", "k_pass_lattice_cubic256.counters.txt")
+    traffic = measured_traffic(srcs, cfile)
+    return {"workload": w["desc"], "value": N * w["R"] * w["sweeps"] * jobs / (sum(run_ms) / 1000.0),
+            "unit": "site-replica move attempts/s", "jobs": jobs,
+            "roofline": {"bound": "hbm", "achieved": B / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": B / avg_s / 1e9 / HBM_PEAK_GBS, "kernel": "k_pass_lattice",
+                         "avg_launch_us": avg_s * 1e6, "bytes_per_launch": B,
+                         "frac_with_moved_ever_reads": B16 / avg_s / 1e9 / HBM_PEAK_GBS,
+                         "traffic": traffic,
+                         "traffic_source": "profiles/k_pass_lattice_cubic256.counters.txt" if traffic else None}}
 
 
 def batch_measure(steps, warmup, sweeps=1000, serial=True):
@@ -655,8 +707,11 @@ def main():
         log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(w)
     if args.workload == "cubic128" and not args.no_extras and args.sweeps is None and args.replicas is None:
-        # After the headline's timed region: the batched and served forms against one job at a
-        # time on the same GPU (their own workloads: --workload batch256 / serve).
+        # After the headline's timed region: the same pass beyond the Infinity Cache (3D
+        # L=256), then the batched and served forms against one job at a time on the same GPU
+        # (their own workloads: --workload cubic256 / batch256 / serve).
+        log("extra: 3D L=256 (HBM regime) ...")
+        result["hbm_regime"] = hbm_regime_measure(stream)
         log("extra: batch of 256 uneven instances ...")
         b = batch_measure(1, 1)
         result["batch256"] = {
