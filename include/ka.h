@@ -267,8 +267,8 @@ int ka_batch_wait_all(ka_batch *b);
 
 /* Options: KA_BOPT_AUTOTUNE (1 default / 0), KA_BOPT_BLOCK (tile = workgroup size: 128,
  * 256 or 512; disables autotuning), KA_BOPT_GRAPH_STEPS (steps per captured graph, default
- * 64; 0 = plain launches), KA_BOPT_CACHE_BUDGET (bytes, default 0 = off; set before the
- * first ka_batch_add): members whose working set (n and f, 2 x 8 x N x n_replicas/64 bytes)
+ * 64; 0 = plain launches), KA_BOPT_CACHE_BUDGET (bytes, default 0 = off; set while the batch
+ * has no members, else KA_ESTATE): members whose working set (n and f, 2 x 8 x N x n_replicas/64 bytes)
  * is at least 1/8 of the budget are large, and a large member starts only while it fits
  * the budget next to the large members still running (or when none runs); otherwise it
  * waits, in the order added, and starts at the step where enough of them have finished.

@@ -637,9 +637,8 @@ extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
         return KA_OK;
       case KA_BOPT_CACHE_BUDGET:
         if (value < 0) return bfail(KA_EINVAL, "cache budget must be >= 0");
-        if (!b->waiting.empty() || b->n_members > 0)
-          for (int k = 0; k < b->n_members; ++k)
-            if (b->sims[(size_t)k]) return bfail(KA_ESTATE, "the cache budget is set before members are added");
+        for (int k = 0; k < b->n_members; ++k)
+          if (b->sims[(size_t)k]) return bfail(KA_ESTATE, "the cache budget is set while the batch has no members");
         b->cache_budget = value;
         return KA_OK;
       default:

@@ -231,6 +231,42 @@ def test_set_state_resume(oracle):
     _observe_equal(sim, orc)
 
 
+@pytest.mark.parametrize("R", [64, 128])
+def test_full_moved_ever_summary_cleared_by_set_state(oracle, R):
+    """General graphs keep a bit per vertex once its moved-ever words are all ones and then
+    skip reading them.  After enough sweeps at m = z-1 (no constraint) every vertex is full;
+    ka_set_state then puts back a state whose f has been cleared, and the run must mark moves
+    again exactly as the oracle does from the same state (global path, one and two words per
+    thread).  The same run without the reset checks the summary's steady state."""
+    N, z, m = 3000, 4, 3
+    g = ka.ka_graph_rrg(N, z, 17)
+    adj, _, _, _ = ka.ka_graph_export(g)
+    og = oracle.graph_from_adjacency(adj)
+    K = oracle.k_from_rho(N, 0.5)
+    _say(f"moved-ever summary: RRG N={N} R={R}")
+    sim = ka.ka_init_k(g, m, K, 8, R)
+    ka.ka_set_option(sim, ka.KA_OPT_PATH, 1)
+    orc = oracle.Sim(og, m, K, 8, range(R))
+    ka.ka_sweep(sim, 60)
+    orc.sweep(60)
+    _state_equal(sim, orc)
+    n, n0, f, t = ka.ka_get_state(sim)
+    assert (f == np.uint64(0xFFFFFFFFFFFFFFFF)).mean() > 0.99     # the summary is in use
+    ka.ka_sweep(sim, 3)                                           # full: f reads skipped
+    orc.sweep(3)
+    _state_equal(sim, orc)
+    _observe_equal(sim, orc)
+    n, n0, f, t = ka.ka_get_state(sim)
+    zero = np.zeros_like(f)
+    ka.ka_set_state(sim, n, n0, zero, t)
+    orc.moved[:] = 0
+    ka.ka_sweep(sim, 2)
+    orc.sweep(2)
+    _state_equal(sim, orc)
+    _observe_equal(sim, orc)
+    sim.free()
+
+
 def test_replica_subset_independence(oracle):
     """Replica b's trajectory does not depend on how many replicas run beside it."""
     g = ka.ka_graph_lattice(2, 16)
