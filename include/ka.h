@@ -210,15 +210,23 @@ int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t *K, int *m
  *                  of the other's.  The overlap needs the runtime to place the two streams
  *                  on different hardware queues; on a shared queue the passes serialize and
  *                  run slower.  Not used while KA_OPT_TIMING is on.  Results are identical
- *                  either way. */
+ *                  either way.
+ *   KA_OPT_TAIL:   general graphs on the global-memory path.  1 (default) = when the class
+ *                  schedule ends in two or more classes of at most 512 edges each (greedy
+ *                  colourings end in a few tiny classes) and one word plane takes at most
+ *                  1 MiB (N * 8 * words per thread bytes), that run of classes is one launch
+ *                  of one workgroup per word plane, classes in order with a barrier between
+ *                  them; 0 = one launch per class.  Results are identical. */
 #define KA_OPT_PATH 1
 #define KA_OPT_TIMING 2
 #define KA_OPT_NOISE 3
 #define KA_OPT_PLANE_STREAMS 4
+#define KA_OPT_TAIL 5
 int ka_set_option(ka_sim *s, int option, int64_t value);
 
 /* Class-pass kernel launches so far (one per class step, or one per word plane and class
- * step when the planes run on their own streams), and among them the number bracketed by
+ * step when the planes run on their own streams; a merged run of tiny graph classes counts
+ * once), and among them the number bracketed by
  * events and their summed duration in milliseconds (synchronises the stream). */
 int ka_timing(ka_sim *s, int64_t *launches, int64_t *timed, double *timed_ms);
 

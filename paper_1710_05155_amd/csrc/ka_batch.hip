@@ -53,37 +53,57 @@ __device__ __forceinline__ void run_lattice_tile(const BatchMember &mb, int loca
   }
 }
 
+// One edge of a graph member (entry k of its class-sorted list, class c).
+template <int WPT>
+__device__ __forceinline__ void member_graph_edge(const BatchMember &mb, u64 *n, u64 *f, int plane, int k,
+                                                  int c, uint32_t t)
+{
+  const size_t st = (size_t)mb.stride;
+  if (mb.fsat) {
+    const FSat sat{mb.fsat, plane * mb.N};
+    switch (mb.z) {
+      case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      case 5: graph_edge<5, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      case 6: graph_edge<6, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
+      default: break;
+    }
+    return;
+  }
+  switch (mb.z) {
+    case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
+    case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
+    case 5: graph_edge<5, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
+    case 6: graph_edge<6, WPT>(n, f, mb.edges, mb.nbr, st, k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
+    default: break;
+  }
+}
+
 template <int BLOCK, int WPT>
 __device__ __forceinline__ void run_graph_tile(const BatchMember &mb, int local, int c, uint32_t t)
 {
   const int bpp = mb.tiles_per_plane;
   const int plane = local / bpp;
   const int blk = local - plane * bpp;
+  const size_t off = (size_t)plane * (size_t)mb.N * WPT;
+  u64 *n = mb.n + off, *f = mb.f + off;
+  if (c == mb.C - 1 && mb.classes > mb.C) {
+    // the merged run of tiny trailing classes: the plane's first tile takes them in order,
+    // with a workgroup barrier between classes (as in the single-instance tail launch; the
+    // condition is the same for every thread of the workgroup)
+    if (blk != 0) return;
+    for (int cc = c; cc < mb.classes; ++cc) {
+      const int b0 = mb.class_start[cc], b1 = mb.class_start[cc + 1];
+      for (int k = b0 + (int)threadIdx.x; k < b1; k += BLOCK) member_graph_edge<WPT>(mb, n, f, plane, k, cc, t);
+      __syncthreads();
+    }
+    return;
+  }
   const int b0 = mb.class_start[c];
   const int count = mb.class_start[c + 1] - b0;
   const int k = blk * BLOCK + (int)threadIdx.x;
   if (k >= count) return;
-  const size_t off = (size_t)plane * (size_t)mb.N * WPT;
-  u64 *n = mb.n + off, *f = mb.f + off;
-  const size_t st = (size_t)mb.stride;
-  if (mb.fsat) {
-    const FSat sat{mb.fsat, plane * mb.N};
-    switch (mb.z) {
-      case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
-      case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
-      case 5: graph_edge<5, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
-      case 6: graph_edge<6, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise, sat); break;
-      default: break;
-    }
-    return;
-  }
-  switch (mb.z) {
-    case 3: graph_edge<3, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
-    case 4: graph_edge<4, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
-    case 5: graph_edge<5, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
-    case 6: graph_edge<6, WPT>(n, f, mb.edges, mb.nbr, st, b0 + k, plane, mb.m, t, (uint32_t)c, mb.key0, mb.key1, mb.noise); break;
-    default: break;
-  }
+  member_graph_edge<WPT>(mb, n, f, plane, b0 + k, c, t);
 }
 
 // Tile table of the segment that starts at `step`: members with `wpt` words per thread

@@ -131,6 +131,7 @@ int tiles_per_plane(const ka_batch *b, int k, int block)
     const int threads = nsub * 64 * ((m.P + 63) / 64);
     return (threads + block - 1) / block;
   }
+  if (m.C == 1 && m.classes > 1) return 1;   // the whole sweep is one merged run
   int biggest = 0;
   for (int c : b->class_sizes[(size_t)k]) biggest = std::max(biggest, c);
   return (biggest + block - 1) / block;
@@ -525,6 +526,8 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
     m.z = s->z;
     m.m = s->m;
     m.C = s->C;
+    m.classes = s->C;
+    if (!s->lattice && s->tail_opt && s->tail_first < s->C) m.C = s->tail_first + 1;   // merged tail
     m.planes = s->planes;
     m.wpt = s->wpt;
     m.key0 = (uint32_t)s->seed;

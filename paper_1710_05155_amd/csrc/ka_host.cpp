@@ -632,7 +632,7 @@ bool plane_split(ka_sim *s)
 #endif
 constexpr int kRowTileLog2 = KA_ROW_TILE_LOG2;
 
-hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
+hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split, int c_end)
 {
   const uint32_t k0 = (uint32_t)s->seed, k1 = (uint32_t)(s->seed >> 32);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -697,7 +697,13 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
     a.key1 = k1;
     a.noise = s->noise;
     a.fsat = s->fsat;
-    err = a.count > 0 ? ka::launch_pass_graph(a, s->z, s->m, s->wpt, s->stream) : hipSuccess;
+    if (c_end > c + 1) {
+      a.class_start = s->class_start_d;
+      a.c_end = (uint32_t)c_end;
+      err = ka::launch_tail_graph(a, s->z, s->m, s->wpt, s->stream);
+    } else {
+      err = a.count > 0 ? ka::launch_pass_graph(a, s->z, s->m, s->wpt, s->stream) : hipSuccess;
+    }
   }
   if (timed) {
     (void)hipEventRecord(e1, s->stream);
@@ -705,6 +711,24 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split)
   }
   s->launches += 1;
   return err;
+}
+
+// First class of the trailing run of classes with at most kTailEdges edges each, which the
+// global path runs in one launch (one workgroup per plane); the class count if that run has
+// fewer than two classes.  Greedy distance-2 colourings end in a few such tiny classes, each
+// of which would otherwise cost a whole launch for a few hundred edges.  The merge is used
+// only for graphs whose words of one plane take at most kTailPlaneBytes: on larger graphs
+// the one CU's gathers for a few hundred edges miss its caches and take longer than the
+// launches they replace (per sweep, 2^14 to 2^16 vertices: 4-7 us less; 2^18 and 2^20:
+// 1 and 4.5 us more).
+constexpr size_t kTailPlaneBytes = (size_t)1 << 20;
+
+int tail_first(const std::vector<int> &class_start)
+{
+  const int C = (int)class_start.size() - 1;
+  int c = C;
+  while (c > 0 && class_start[(size_t)c] - class_start[(size_t)c - 1] <= ka::kTailEdges) --c;
+  return C - c >= 2 ? c : C;
 }
 
 constexpr int64_t kLdsChunk = 20000;            // sweeps per LDS-resident launch
@@ -903,9 +927,12 @@ hipError_t sweep_global(ka_sim *s, int64_t n)
     for (int k = 0; k < 2 && e == hipSuccess; ++k) e = hipStreamWaitEvent(s->plane_stream[k], s->fork_ev, 0);
     if (e != hipSuccess) return e;
   }
+  // general graphs: the trailing run of tiny classes in one launch
+  const int tail = (!s->lattice && s->tail_opt) ? s->tail_first : s->C;
   for (int64_t q = 0; q < n && e == hipSuccess; ++q) {
     const uint32_t t = (uint32_t)(s->t + q);
-    for (int c = 0; c < s->C && e == hipSuccess; ++c) e = launch_class(s, c, t, split);
+    for (int c = 0; c < tail && e == hipSuccess; ++c) e = launch_class(s, c, t, split, c + 1);
+    if (tail < s->C && e == hipSuccess) e = launch_class(s, tail, t, split, s->C);
   }
   if (split) {
     // joined even after a failed launch, so that later work on the sim's stream stays
@@ -1219,6 +1246,8 @@ extern "C" int ka_init_k(const ka_graph *g, int m, int64_t K, uint64_t seed, int
       }
       // The sim keeps the plan alive, so the copies below may run after the graph is freed.
       s->plan = plan;
+      // merged only while one plane's words are small enough to stay near the one CU
+      s->tail_first = (size_t)s->N * 8u * (size_t)s->wpt <= kTailPlaneBytes ? tail_first(plan->class_start) : s->C;
       const std::vector<int32_t> &site_of = plan->site_of;
       const std::vector<int4> &rec = plan->rec;
       const std::vector<int32_t> &nbr = plan->nbr;
@@ -1697,6 +1726,11 @@ extern "C" int ka_set_option(ka_sim *s, int option, int64_t value)
     if (option == KA_OPT_PLANE_STREAMS) {
       if (value != 0 && value != 1) return fail(KA_EINVAL, "plane streams must be 0 or 1");
       s->plane_streams = (int)value;
+      return KA_OK;
+    }
+    if (option == KA_OPT_TAIL) {
+      if (value != 0 && value != 1) return fail(KA_EINVAL, "tail merging must be 0 or 1");
+      s->tail_opt = (int)value;
       return KA_OK;
     }
     return fail(KA_EINVAL, "unknown option %d", option);

@@ -69,6 +69,10 @@ struct PassGraph {
   // summary of full moved-ever elements: bit plane*N + i set once every word of f at
   // element i of plane `plane` is all ones (null: f always read where an exchange happens)
   uint32_t *fsat;
+  // merged run of small classes (launch_tail_graph): classes c .. c_end - 1, bounds from
+  // class_start ([C+1], device); first, count and blocks_per_plane are not used there
+  const int *class_start;
+  uint32_t c_end;
 };
 
 // Whole sweep loop inside one workgroup per plane (plane in LDS).
@@ -138,6 +142,10 @@ struct ObserveArgs {
 // Launchers (ka_kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_pass_lattice(const PassLattice &a, int m, int wpt, hipStream_t s);
 hipError_t launch_pass_graph(const PassGraph &a, int z, int m, int wpt, hipStream_t s);
+// Classes a.c .. a.c_end - 1 of a general graph, each of at most kTailEdges edges, in one
+// launch of one workgroup per plane.
+constexpr int kTailEdges = 512;
+hipError_t launch_tail_graph(const PassGraph &a, int z, int m, int wpt, hipStream_t s);
 hipError_t launch_sweep_lds(const SweepLds &a, bool lattice, int zdeg, int m, int wpt,
                             size_t lds_bytes, hipStream_t s);
 hipError_t launch_init(const InitArgs &a, int R, int wpt, hipStream_t s);
@@ -211,7 +219,9 @@ struct BatchMember {
   int kind;                    // 0 lattice, 1 graph
   int d, L, Q, P, N;           // lattice geometry (N for both)
   unsigned long long qinv;     // lattice: lattice_qinv(Q)
-  int z, m, C, planes, wpt;
+  int z, m, C, planes, wpt;    // C: steps per sweep
+  int classes;                 // graphs: classes per sweep; when above C, the last step runs
+                               // classes C-1 .. classes-1 in one workgroup per plane
   int noise;                   // 0: acceptance bit per replica, 1: shared by all replicas
   uint32_t key0, key1;
   uint32_t t0;

@@ -79,6 +79,9 @@ struct ka_sim {
   int path_opt = 0;
   int noise = 0;                  // KA_OPT_NOISE
   int plane_streams = 0;          // KA_OPT_PLANE_STREAMS
+  int tail_opt = 1;               // KA_OPT_TAIL
+  int tail_first = 0;             // general graphs: first class of the trailing run of classes
+                                  // of at most kTailEdges edges (C if that run is shorter than 2)
   size_t lds_bytes = 0;
   bool lds_fits = false;
   ka::u64 *lds_acc = nullptr;     // LDS lattice sweep: pre-generated acceptance words

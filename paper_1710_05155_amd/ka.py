@@ -22,6 +22,7 @@ KA_OPT_PATH = 1
 KA_OPT_TIMING = 2
 KA_OPT_NOISE = 3
 KA_OPT_PLANE_STREAMS = 4
+KA_OPT_TAIL = 5
 
 # Every symbol include/ka.h declares.
 SYMBOLS = (

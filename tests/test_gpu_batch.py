@@ -271,6 +271,9 @@ def test_cache_budget_members_equal_solo(budget, expected_steps):
     sims = []
     for spec, g in zip(BUDGET_MEMBERS, graphs):
         s = _make(spec, g)
+        # one step per class, as in the step counts above (every class of this graph is
+        # small, so by default its whole sweep would be one merged step)
+        ka.ka_set_option(s, ka.KA_OPT_TAIL, 0)
         ka.ka_batch_add(b, s, spec[7])
         sims.append(s)
     assert graphs[2].C * 3 == 45
@@ -304,3 +307,62 @@ def test_cache_budget_set_before_members(graphs):
     assert e.value.code == ka.KA_EINVAL
     b.free()
     s.free()
+
+
+TAIL_MEMBERS = [
+    # colourings ending in tiny classes: 17 classes, the last 4 (415, 104, 12, 1 edges)
+    # merged; 11 classes, the last 3 merged; 22 classes, the last 3 merged
+    ("rrg", 16384, 4, 2, 0.6, 64, 51, 3),
+    ("rrg", 8192, 3, 1, 0.55, 128, 52, 4),
+    ("rrg", 16384, 5, 3, 0.7, 192, 53, 2),
+    ("rrg", 2000, 4, 2, 0.65, 128, 54, 3),      # every class small: one step per sweep
+    ("lat", (3, 12), 6, 3, 0.8, 64, 55, 2),
+]
+
+
+def _tail_first(class_sizes, most=512):
+    """First class of the trailing run of classes with at most `most` edges each, or the
+    class count if that run holds fewer than two classes."""
+    C = len(class_sizes)
+    c = C
+    while c > 0 and class_sizes[c - 1] <= most:
+        c -= 1
+    return c if C - c >= 2 else C
+
+
+@pytest.mark.parametrize("tail", [1, 0])
+def test_batch_merged_tail_classes(tail):
+    """A graph member whose colouring ends in tiny classes runs that trailing run as one step
+    (one workgroup per plane takes the classes in order), unless KA_OPT_TAIL is 0 on the sim;
+    the projected steps count the run once, and either way every member ends in its solo
+    state."""
+    _say(f"batch: merged tail classes, tail={tail}")
+    graphs = [_graph(spec) for spec in TAIL_MEMBERS]
+    solo = []
+    for spec, g in zip(TAIL_MEMBERS, graphs):
+        s = _make(spec, g)
+        ka.ka_sweep(s, spec[7])
+        solo.append(ka.ka_get_state(s))
+        s.free()
+    b = ka.ka_batch_create(8)
+    sims, expected = [], 0
+    for spec, g in zip(TAIL_MEMBERS, graphs):
+        s = _make(spec, g)
+        ka.ka_set_option(s, ka.KA_OPT_TAIL, tail)
+        ka.ka_batch_add(b, s, spec[7])
+        sims.append(s)
+        steps_per_sweep = g.C
+        if spec[0] == "rrg" and tail:
+            _, _, _, ec = ka.ka_graph_export(g)
+            first = _tail_first(np.bincount(ec, minlength=g.C))
+            assert first <= g.C - 2
+            steps_per_sweep = first + 1
+        expected = max(expected, steps_per_sweep * spec[7])
+    assert ka.ka_batch_steps_left(b) == expected
+    ka.ka_batch_wait_all(b)
+    for k, (s, ref) in enumerate(zip(sims, solo)):
+        for x, y in zip(ka.ka_get_state(s), ref):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), k
+    b.free()
+    for s in sims:
+        s.free()

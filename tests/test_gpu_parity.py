@@ -36,9 +36,11 @@ def _observe_equal(sim, orc):
     assert np.array_equal(dens, odens) and np.array_equal(ov, oov) and np.array_equal(pers, opers)
 
 
-def _check_case(oracle, lib_graph, or_graph, m, K, seed, R, chunks, path):
-    _say(f"N={or_graph.N} z={or_graph.z} m={m} K={K} R={R} path={path} chunks={chunks}")
+def _check_case(oracle, lib_graph, or_graph, m, K, seed, R, chunks, path, options=()):
+    _say(f"N={or_graph.N} z={or_graph.z} m={m} K={K} R={R} path={path} chunks={chunks} options={options}")
     sim = ka.ka_init_k(lib_graph, m, K, seed, R)
+    for opt, value in options:
+        ka.ka_set_option(sim, opt, value)
     if path:
         try:
             ka.ka_set_option(sim, ka.KA_OPT_PATH, path)
@@ -108,6 +110,68 @@ def test_rrg_parity(oracle, N, z, m, rho, R, path):
     og = oracle.graph_from_adjacency(oadj)
     K = oracle.k_from_rho(N, rho)
     _check_case(oracle, g, og, m, K, 99 + N, R, [1, 3, 5], path)
+
+
+@pytest.mark.parametrize("N,z,m,rho,R", RRG_CASES)
+def test_rrg_parity_one_launch_per_class(oracle, N, z, m, rho, R):
+    """The same cases on the global path with every class in a launch of its own (these
+    graphs' classes are all small, so by default a whole sweep is one merged launch)."""
+    g = ka.ka_graph_rrg(N, z, 17)
+    oadj, _ = oracle.rrg_adjacency(N, z, 17)
+    og = oracle.graph_from_adjacency(oadj)
+    K = oracle.k_from_rho(N, rho)
+    _check_case(oracle, g, og, m, K, 99 + N, R, [1, 3, 5], 1, options=((ka.KA_OPT_TAIL, 0),))
+
+
+def _tail_first(class_sizes, most=512):
+    """First class of the trailing run of classes with at most `most` edges each, or the
+    class count if that run holds fewer than two classes."""
+    C = len(class_sizes)
+    c = C
+    while c > 0 and class_sizes[c - 1] <= most:
+        c -= 1
+    return c if C - c >= 2 else C
+
+
+@pytest.mark.parametrize("N,z,m,rho,R,mixed", [
+    (16384, 4, 2, 0.6, 64, True),
+    (16384, 5, 3, 0.7, 192, True),
+    (8192, 3, 1, 0.55, 128, True),
+    (2000, 4, 2, 0.65, 192, False),
+])
+def test_tail_classes_one_launch(oracle, N, z, m, rho, R, mixed):
+    """Greedy colourings end in a few classes of a few hundred edges or fewer; on the global
+    path that trailing run is one launch with one workgroup per word plane.  Runs with and
+    without the merge equal the oracle, and the launch counts show which ran."""
+    g = ka.ka_graph_rrg(N, z, 23)
+    adj, _, _, ec = ka.ka_graph_export(g)
+    og = oracle.graph_from_adjacency(adj)
+    sizes = np.bincount(ec, minlength=og.C)
+    assert N * 8 * (2 if R % 128 == 0 else 1) <= 1 << 20    # small enough for the merge
+    tail = _tail_first(sizes)
+    if mixed:
+        assert 0 < tail <= og.C - 2, sizes        # large classes, then a merged run
+    else:
+        assert tail == 0, sizes                    # every class small: one launch per sweep
+    K = oracle.k_from_rho(N, rho)
+    _say(f"tail classes: RRG N={N} z={z} R={R} classes={og.C} tail from {tail}")
+    sims = []
+    for opt in (1, 0):
+        sim = ka.ka_init_k(g, m, K, 5, R)
+        ka.ka_set_option(sim, ka.KA_OPT_PATH, 1)
+        ka.ka_set_option(sim, ka.KA_OPT_TAIL, opt)
+        sims.append(sim)
+    orc = oracle.Sim(og, m, K, 5, range(R))
+    for n in (1, 4):
+        for sim in sims:
+            ka.ka_sweep(sim, n)
+        orc.sweep(n)
+        for sim in sims:
+            _state_equal(sim, orc)
+            _observe_equal(sim, orc)
+    assert [ka.ka_timing(sim)[0] for sim in sims] == [5 * (tail + 1), 5 * og.C]
+    for sim in sims:
+        sim.free()
 
 
 LAYERED_CASES = [
@@ -231,21 +295,24 @@ def test_set_state_resume(oracle):
     _observe_equal(sim, orc)
 
 
+@pytest.mark.parametrize("tail", [1, 0])
 @pytest.mark.parametrize("R", [64, 128])
-def test_full_moved_ever_summary_cleared_by_set_state(oracle, R):
+def test_full_moved_ever_summary_cleared_by_set_state(oracle, R, tail):
     """General graphs keep a bit per vertex once its moved-ever words are all ones and then
     skip reading them.  After enough sweeps at m = z-1 (no constraint) every vertex is full;
     ka_set_state then puts back a state whose f has been cleared, and the run must mark moves
     again exactly as the oracle does from the same state (global path, one and two words per
-    thread).  The same run without the reset checks the summary's steady state."""
+    thread, with the trailing tiny classes merged into one launch or not).  The same run
+    without the reset checks the summary's steady state."""
     N, z, m = 3000, 4, 3
     g = ka.ka_graph_rrg(N, z, 17)
     adj, _, _, _ = ka.ka_graph_export(g)
     og = oracle.graph_from_adjacency(adj)
     K = oracle.k_from_rho(N, 0.5)
-    _say(f"moved-ever summary: RRG N={N} R={R}")
+    _say(f"moved-ever summary: RRG N={N} R={R} tail={tail}")
     sim = ka.ka_init_k(g, m, K, 8, R)
     ka.ka_set_option(sim, ka.KA_OPT_PATH, 1)
+    ka.ka_set_option(sim, ka.KA_OPT_TAIL, tail)
     orc = oracle.Sim(og, m, K, 8, range(R))
     ka.ka_sweep(sim, 60)
     orc.sweep(60)
