@@ -662,6 +662,8 @@ def main():
         expected_R = {"cubic128": 256, "cubic256": 256, "rrg20": 64}.get(args.workload)
         if counters and R == expected_R and not args.plane_streams and sweeps == WORKLOADS[args.workload]["sweeps"]:
             srcs = [os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")]
+            if w["kind"] != "lattice":
+                srcs.append(os.path.join(csrc, "ka_plan.cpp"))   # the graph's device numbering
             cfile = os.path.join(ROOT, "profiles", counters)
             traffic = measured_traffic(srcs, cfile)
             valu = measured_traffic(srcs, cfile, key="valu_busy_pct")

@@ -10,7 +10,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libka.so")
 ARCH = os.environ.get("KA_OFFLOAD_ARCH", "gfx950")
-SOURCES = ("ka_pass.hip", "ka_tail.hip", "ka_lds.hip", "ka_batch.hip", "ka_pairs.hip", "ka_probe.hip", "ka_host.cpp", "ka_batch_host.cpp", "ka_server.cpp")
+SOURCES = ("ka_pass.hip", "ka_tail.hip", "ka_lds.hip", "ka_batch.hip", "ka_pairs.hip", "ka_probe.hip", "ka_host.cpp", "ka_plan.cpp", "ka_batch_host.cpp", "ka_server.cpp")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC]
 # No packed-FP32 instructions in any device code.

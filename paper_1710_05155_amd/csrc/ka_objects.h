@@ -24,6 +24,13 @@ struct GraphPlan {
   std::vector<int32_t> nbr;       // [2(z-1)][E] neighbour lists of rec
 };
 
+struct ka_graph;
+
+// The device schedule of a general graph (vertex numbering, class-sorted records, neighbour
+// lists), built on first use and kept in the graph: later ka_init calls on the same graph only
+// copy it to the device.  Null if host memory runs out.  ka_plan.cpp.
+std::shared_ptr<const GraphPlan> graph_plan(const ka_graph *g);
+
 struct ka_graph {
   int lattice = 0;  // 1: hypercubic lattice (d, L); 0: general z-regular graph
   int d = 0, L = 0;
