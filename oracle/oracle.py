@@ -18,7 +18,8 @@ from dataclasses import dataclass
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# KA_ORACLE_LIB names another build of the same source (the sanitizer test uses it)
+LIB_PATH = os.environ.get("KA_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 _lib = None
 

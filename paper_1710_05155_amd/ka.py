@@ -11,7 +11,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libka.so")
+# KA_LIB names another build of libka (for example one with the host code under sanitizers)
+LIB_PATH = os.environ.get("KA_LIB") or os.path.join(PKG, "libka.so")
 
 KA_OK = 0
 KA_EINVAL = -1
