@@ -96,11 +96,11 @@ int edge_owner_part(int pu, int pv, int64_t q) { return pu == pv || (q & 1) == 0
 constexpr int kGraphParts = 8;              // one per XCD
 constexpr int64_t kGraphPartMinN = 1 << 19; // below this a word plane fits one 4 MB L2
 
+}  // namespace
+
 // The device schedule of a general graph (see GraphPlan), built on first use and kept in the
 // graph: later ka_init calls on the same graph only copy it to the device.  Returns null if
 // host memory runs out.
-}  // namespace
-
 std::shared_ptr<const GraphPlan> graph_plan(const ka_graph *g)
 {
   std::lock_guard<std::mutex> lock(g->plan_mu);
@@ -108,7 +108,7 @@ std::shared_ptr<const GraphPlan> graph_plan(const ka_graph *g)
   try {
     auto p = std::make_shared<GraphPlan>();
     // Device numbering of the vertices: part by part (see partition_vertices), then by the
-    // set of other parts a vertex borders, breadth-first inside each group.
+    // set of parts whose XCDs read the vertex, breadth-first inside each group.
     const int64_t Nv = g->N;
     const int z = g->z;
     const std::vector<int> part = partition_vertices(g, Nv >= kGraphPartMinN ? kGraphParts : 1);
