@@ -191,9 +191,12 @@ def hbm_regime_measure(stream, jobs=2):
     N, W = g.N, w["R"] // 64
     sweep_ms = sum(run_ms) - jobs * obs_ms
     avg_s = sweep_ms / launches / 1000.0
-    B = class_pass_bytes(w, N, W)
-    B16 = class_pass_bytes(w, N, W, with_moved_ever=True)
-    srcs = [os.path.join(ROOT, "paper_1710_05155_amd", "csrc", f) for f in ("ka_device.h", "ka_pass.hip")]
+    # the model is per class step over all words; a step is one launch per group of word
+    # planes (the words of this lattice run one group at a time), so scale to one launch
+    per_launch = w["sweeps"] * g.C * jobs / launches
+    B = class_pass_bytes(w, N, W) * per_launch
+    B16 = class_pass_bytes(w, N, W, with_moved_ever=True) * per_launch
+    srcs = [os.path.join(ROOT, "paper_1710_05155_amd", "csrc", f) for f in ("ka_device.h", "ka_pass.hip", "ka_host.cpp")]
     cfile = os.path.join(ROOT, "profiles", "k_pass_lattice_cubic256.counters.txt")
     traffic = measured_traffic(srcs, cfile)
     return {"workload": w["desc"], "value": N * w["R"] * w["sweeps"] * jobs / (sum(run_ms) / 1000.0),
@@ -661,7 +664,8 @@ def main():
                     "rrg20": "k_pass_graph_rrg20.counters.txt"}.get(args.workload)
         expected_R = {"cubic128": 256, "cubic256": 256, "rrg20": 64}.get(args.workload)
         if counters and R == expected_R and not args.plane_streams and sweeps == WORKLOADS[args.workload]["sweeps"]:
-            srcs = [os.path.join(csrc, "ka_device.h"), os.path.join(csrc, "ka_pass.hip")]
+            # kernels, and the host code that chooses the launches (plane groups, chunk order)
+            srcs = [os.path.join(csrc, f) for f in ("ka_device.h", "ka_pass.hip", "ka_host.cpp")]
             if w["kind"] != "lattice":
                 srcs.append(os.path.join(csrc, "ka_plan.cpp"))   # the graph's device numbering
             cfile = os.path.join(ROOT, "profiles", counters)

@@ -87,6 +87,8 @@ struct ka_sim {
   int noise = 0;                  // KA_OPT_NOISE
   int plane_streams = 0;          // KA_OPT_PLANE_STREAMS
   int tail_opt = 1;               // KA_OPT_TAIL
+  int plane_group = 0;            // lattices: planes per launch group chosen at init (0: all)
+  int plane_group_opt = -1;       // KA_OPT_PLANE_GROUPS (-1: plane_group)
   int tail_first = 0;             // general graphs: first class of the trailing run of classes
                                   // of at most kTailEdges edges (C if that run is shorter than 2)
   size_t lds_bytes = 0;

@@ -24,6 +24,7 @@ KA_OPT_TIMING = 2
 KA_OPT_NOISE = 3
 KA_OPT_PLANE_STREAMS = 4
 KA_OPT_TAIL = 5
+KA_OPT_PLANE_GROUPS = 6
 
 # Every symbol include/ka.h declares.
 SYMBOLS = (

@@ -118,21 +118,24 @@ def test_rrg20_graph_and_sampled_replicas(oracle):
         sim.free()
 
 
-@pytest.mark.parametrize("R", [256, 64])
-def test_cubic256_tiled_order_sampled_replicas(oracle, R):
+@pytest.mark.parametrize("R,groups", [(256, 4), (128, 2), (64, 1)])
+def test_cubic256_tiled_order_sampled_replicas(oracle, R, groups):
     """3D L=256 (Q = 64): the class pass visits chunk rows in tiles along p1 (a permutation
-    of the edges of a class, which commute).  Replicas 0 and R-1 match the oracle bit for bit
-    after 2 sweeps, with word pairs (256 replicas) and single words (64)."""
+    of the edges of a class, which commute), and with more than one 64-replica word the n and
+    f of all words exceed the 256 MiB Infinity Cache, so the words run one at a time (one
+    word per plane, one launch per word and class step).  Replicas 0, 64 (when present) and
+    R-1 match the oracle bit for bit after 2 sweeps."""
     g = ka.ka_graph_lattice(3, 256)
     og = oracle.lattice(3, 256)
     K = oracle.k_from_rho(og.N, 0.85)
-    _say(f"cubic256 R={R}: 2 sweeps, replicas 0 and {R - 1}")
+    reps = sorted({0, min(64, R - 1), R - 1})
+    _say(f"cubic256 R={R}: 2 sweeps, replicas {reps}")
     sim = ka.ka_init(g, 3, 0.85, 7, R)
     assert ka.ka_sim_path(sim) == 1
     dens, ov, pers = ka.ka_run(sim, [1, 2])
+    assert ka.ka_timing(sim)[0] == 2 * 12 * groups     # one launch per word group and class
     n, n0, f, t = ka.ka_get_state(sim)
     sim.free()
-    reps = [0, R - 1]
     orc = oracle.Sim(og, 3, K, 7, reps)
     for q, tt in enumerate([1, 2]):
         orc.sweep(tt - orc.t)

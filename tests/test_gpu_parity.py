@@ -279,6 +279,34 @@ def test_plane_streams_identical(oracle, d, L, R):
         assert np.array_equal(row.astype(np.uint8), orc.occ[q])
 
 
+@pytest.mark.parametrize("d,L,R,group", [(3, 12, 256, 1), (2, 16, 192, 2), (3, 8, 320, 2), (2, 12, 128, 1)])
+def test_plane_groups_match_oracle(oracle, d, L, R, group):
+    """Word planes run group by group (each group through the whole call's sweeps, as large
+    lattices do to keep a group's n and f in the Infinity Cache): the result equals the
+    oracle's, with groups of one or two planes, a short last group, and the ordinary
+    all-planes launch in between; the launch count shows the grouping."""
+    g = ka.ka_graph_lattice(d, L)
+    og = oracle.lattice(d, L)
+    m = d + 1 if d == 3 else 2
+    K = oracle.k_from_rho(og.N, 0.8)
+    _say(f"plane groups: {d}D L={L} R={R} group={group}")
+    sim = ka.ka_init_k(g, m, K, 21, R)
+    ka.ka_set_option(sim, ka.KA_OPT_PATH, 1)
+    W = R // 64
+    planes = W // 2 if W % 2 == 0 else W
+    orc = oracle.Sim(og, m, K, 21, range(R))
+    expected = 0
+    for n, grp in ((3, group), (2, 0), (4, group)):
+        ka.ka_set_option(sim, ka.KA_OPT_PLANE_GROUPS, grp)
+        ka.ka_sweep(sim, n)
+        orc.sweep(n)
+        _state_equal(sim, orc)
+        _observe_equal(sim, orc)
+        expected += n * og.C * (-(-planes // grp) if grp else 1)
+    assert ka.ka_timing(sim)[0] == expected
+    sim.free()
+
+
 def test_set_state_resume(oracle):
     """Checkpoint/resume: a state put back with ka_set_state continues exactly."""
     g = ka.ka_graph_lattice(2, 12)
