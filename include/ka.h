@@ -217,14 +217,15 @@ int ka_sim_info(const ka_sim *s, int64_t *N, int *n_replicas, int64_t *K, int *m
  *                  1 MiB (N * 8 * words per thread bytes), that run of classes is one launch
  *                  of one workgroup per word plane, classes in order with a barrier between
  *                  them; 0 = one launch per class.  Results are identical.
- *   KA_OPT_PLANE_GROUPS: lattices on the global-memory path.  -1 (default) = the choice made
- *                  at ka_init: when the sim's n and f (16 bytes per site and 64 replicas)
+ *   KA_OPT_PLANE_GROUPS: the global-memory path.  -1 (default) = the choice made
+ *                  at ka_init: when a lattice sim's n and f (16 bytes per site and 64 replicas)
  *                  exceed 256 MiB, its word planes run in groups whose n and f fit 256 MiB
  *                  (the MI355X Infinity Cache), each group through a whole ka_sweep call (or
  *                  the sweeps between two ka_run observations) before the next, so that its
  *                  class passes find n and f in the cache; ka_init then also stores one word
- *                  per plane when a group holds a single word.  0 = every plane in each launch;
- *                  k >= 1 = groups of k planes.  Not used while KA_OPT_PLANE_STREAMS is on.
+ *                  per plane when a group holds a single word (general graphs: all planes in
+ *                  each launch).  0 = every plane in each launch; k >= 1 = groups of k planes
+ *                  (lattices and graphs).  Not used while KA_OPT_PLANE_STREAMS is on.
  *                  Results are identical. */
 #define KA_OPT_PATH 1
 #define KA_OPT_TIMING 2

@@ -63,6 +63,7 @@ struct PassGraph {
   int count;                 // edges in the class
   int noise;                 // 0: acceptance bit per replica, 1: shared by all replicas
   int N;
+  int plane0;                // first plane of this launch
   int planes;
   int blocks_per_plane;
   uint32_t t, c, key0, key1;

@@ -68,8 +68,9 @@ template <int Z, int WPT, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void k_pass_graph(PassGraph a, int m)
 {
   const int lin = xcd_remap(blockIdx.x, gridDim.x);
-  const int plane = lin / a.blocks_per_plane;
-  const int blk = lin - plane * a.blocks_per_plane;
+  const int pl = lin / a.blocks_per_plane;
+  const int blk = lin - pl * a.blocks_per_plane;
+  const int plane = a.plane0 + pl;
   const int k = blk * BLOCK + (int)threadIdx.x;
   if (k >= a.count) return;
   const size_t off = (size_t)plane * (size_t)a.N * WPT;

@@ -19,7 +19,7 @@ using namespace dev;
 template <int Z, int WPT>
 __global__ __launch_bounds__(kTailEdges) void k_tail_graph(PassGraph a, int m)
 {
-  const int plane = (int)blockIdx.x;
+  const int plane = a.plane0 + (int)blockIdx.x;
   const size_t off = (size_t)plane * (size_t)a.N * WPT;
   u64 *n = a.n + off, *f = a.f + off;
   for (uint32_t c = a.c; c < a.c_end; ++c) {

@@ -307,6 +307,27 @@ def test_plane_groups_match_oracle(oracle, d, L, R, group):
     sim.free()
 
 
+@pytest.mark.parametrize("N,z,R,group", [(3000, 4, 256, 1), (2000, 5, 192, 2), (16384, 4, 320, 3)])
+def test_plane_groups_graph_match_oracle(oracle, N, z, R, group):
+    """The same grouping on random regular graphs, with the trailing tiny classes merged into
+    one launch per group (the merged launch takes only its group's planes)."""
+    g = ka.ka_graph_rrg(N, z, 29)
+    adj, _, _, _ = ka.ka_graph_export(g)
+    og = oracle.graph_from_adjacency(adj)
+    K = oracle.k_from_rho(N, 0.6)
+    _say(f"plane groups: RRG N={N} z={z} R={R} group={group}")
+    sim = ka.ka_init_k(g, 2, K, 23, R)
+    ka.ka_set_option(sim, ka.KA_OPT_PATH, 1)
+    orc = oracle.Sim(og, 2, K, 23, range(R))
+    for n, grp in ((2, group), (1, 0), (3, group)):
+        ka.ka_set_option(sim, ka.KA_OPT_PLANE_GROUPS, grp)
+        ka.ka_sweep(sim, n)
+        orc.sweep(n)
+        _state_equal(sim, orc)
+        _observe_equal(sim, orc)
+    sim.free()
+
+
 def test_set_state_resume(oracle):
     """Checkpoint/resume: a state put back with ka_set_state continues exactly."""
     g = ka.ka_graph_lattice(2, 12)
