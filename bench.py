@@ -19,10 +19,11 @@ separate launches on two streams that overlap, and this figure is each launch's 
 wall time (the launches' own durations overlap and are longer).  Last, the oracle's rate on
 a bounded sample on this host's cores.
 
-After the headline (default workload only), the batched form (256 uneven instances) and the
-continuous-batching server (a Poisson trace, --jobs jobs at --rate per second and at half the
-measured capacity) are measured against one job at a time and added as "batch256" and
-"serve"; --no-extras skips them.
+After the headline (default workload only): the same pass on 3D L=256 x 256 replicas, whose
+state exceeds the 256 MiB Infinity Cache, so that its words run one at a time ("hbm_regime");
+then the batched form (256 uneven instances) and the continuous-batching server (a Poisson
+trace, --jobs jobs at --rate per second and at half the measured capacity), measured against
+one job at a time ("batch256", "serve").  --no-extras skips them.
 
 Usage: python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--workload cubic128]
 """
@@ -157,8 +158,9 @@ def graph_bytes_model(adj, eu, ev, ec, C, z, W):
 
 def hbm_regime_measure(stream, jobs=2):
     """3D L=256 x 256 replicas, rho = 0.85, 200 sweeps per job with the 38-point log grid cut at
-    200 (state 3 x 512 MiB, beyond the 256 MiB Infinity Cache): rate and the class pass's
-    roofline under the 12 B model, timed like the headline (HIP events around each job's
+    200 (state 3 x 512 MiB, beyond the 256 MiB Infinity Cache; the library runs its four words
+    one at a time, one launch per word and class step): rate and the class pass's roofline
+    under the 12 B model, per launch, timed like the headline (HIP events around each job's
     sweep loop, less the observations timed on their own)."""
     import torch
     from paper_1710_05155_amd import ka
@@ -716,7 +718,7 @@ def main():
         # After the headline's timed region: the same pass beyond the Infinity Cache (3D
         # L=256), then the batched and served forms against one job at a time on the same GPU
         # (their own workloads: --workload cubic256 / batch256 / serve).
-        log("extra: 3D L=256 (HBM regime) ...")
+        log("extra: 3D L=256 (state beyond the Infinity Cache) ...")
         result["hbm_regime"] = hbm_regime_measure(stream)
         log("extra: batch of 256 uneven instances ...")
         b = batch_measure(1, 1)
