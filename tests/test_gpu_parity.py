@@ -304,6 +304,10 @@ def test_plane_groups_match_oracle(oracle, d, L, R, group):
         _observe_equal(sim, orc)
         expected += n * og.C * (-(-planes // grp) if grp else 1)
     assert ka.ka_timing(sim)[0] == expected
+    for bad in (-2, planes + 1):
+        with pytest.raises(ka.KaError) as err:
+            ka.ka_set_option(sim, ka.KA_OPT_PLANE_GROUPS, bad)
+        assert err.value.code == ka.KA_EINVAL
     sim.free()
 
 
