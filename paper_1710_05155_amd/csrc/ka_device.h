@@ -24,8 +24,33 @@ namespace dev {
 
 
 // ------------------------------------------------------------------------------------
+// Three-input bitwise functions in one gfx950 instruction (v_bitop3_b32) per 32 bits.  The
+// 8-bit truth table is the function evaluated on the byte patterns 0xF0, 0xCC, 0xAA standing
+// for its first, second and third input.
+// ------------------------------------------------------------------------------------
+constexpr uint32_t kTTXor3 = (0xF0u ^ 0xCCu ^ 0xAAu) & 0xFFu;                           // a ^ b ^ c
+constexpr uint32_t kTTMaj = ((0xF0u & 0xCCu) | (0xF0u & 0xAAu) | (0xCCu & 0xAAu)) & 0xFFu; // majority
+constexpr uint32_t kTTAnd3 = (0xF0u & 0xCCu & 0xAAu) & 0xFFu;                           // a & b & c
+constexpr uint32_t kTTXorAnd = ((0xF0u ^ 0xCCu) & 0xAAu) & 0xFFu;                       // (a ^ b) & c
+constexpr uint32_t kTTXorOfAnd = (0xF0u ^ (0xCCu & 0xAAu)) & 0xFFu;                     // a ^ (b & c)
+
+template <uint32_t TT>
+__device__ __forceinline__ uint32_t bit3(uint32_t a, uint32_t b, uint32_t c)
+{
+  return __builtin_amdgcn_bitop3_b32(a, b, c, TT);
+}
+
+template <uint32_t TT>
+__device__ __forceinline__ u64 bit3(u64 a, u64 b, u64 c)
+{
+  return (u64)bit3<TT>((uint32_t)a, (uint32_t)b, (uint32_t)c) |
+         ((u64)bit3<TT>((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32);
+}
+
+// ------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).  The round keys depend only on the
-// seed, so they stay in scalar registers; each round is two 32x32->64 multiplies and xors.
+// seed, so they stay in scalar registers; each round is two 32x32->64 multiplies and two
+// three-way xors.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
 {
@@ -34,9 +59,9 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
     const u64 p0 = (u64)0xD2511F53u * (u64)c.x;
     const u64 p1 = (u64)0xCD9E8D57u * (u64)c.z;
     uint4 y;
-    y.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
+    y.x = bit3<kTTXor3>((uint32_t)(p1 >> 32), c.y, k0);
     y.y = (uint32_t)p1;
-    y.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
+    y.z = bit3<kTTXor3>((uint32_t)(p0 >> 32), c.w, k1);
     y.w = (uint32_t)p0;
     c = y;
     k0 += 0x9E3779B9u;
@@ -113,9 +138,8 @@ __device__ __forceinline__ void st(u64 *base, int idx, const Elem<WPT> &e)
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ void full_add(u64 a, u64 b, u64 c, u64 &s, u64 &carry)
 {
-  const u64 t = a ^ b;
-  s = t ^ c;
-  carry = (t & c) | (~t & a);
+  s = bit3<kTTXor3>(a, b, c);
+  carry = bit3<kTTMaj>(a, b, c);
 }
 
 template <int K>
@@ -133,9 +157,8 @@ __device__ __forceinline__ void bitsum(const u64 (&x)[K], u64 &s0, u64 &s1, u64 
     u64 a0, a1;
     full_add(x[0], x[1], x[2], a0, a1);
     s0 = a0 ^ x[3];
-    const u64 b1 = a0 & x[3];
-    s1 = a1 ^ b1;
-    s2 = a1 & b1;
+    s1 = bit3<kTTXorOfAnd>(a1, a0, x[3]);   // a1 ^ (a0 & x3)
+    s2 = bit3<kTTAnd3>(a1, a0, x[3]);
   } else if constexpr (K == 5) {
     u64 a0, a1, b1;
     full_add(x[0], x[1], x[2], a0, a1);
@@ -203,7 +226,7 @@ __device__ __forceinline__ void exchange(Elem<WPT> &ni, Elem<WPT> &nj, const Ele
     }
     const u64 Ai = activity<K>(ai, m);
     const u64 Aj = activity<K>(aj, m);
-    d[w] = (ni.w[w] ^ nj.w[w]) & Ai & Aj & r[w];
+    d[w] = bit3<kTTAnd3>(bit3<kTTXorAnd>(ni.w[w], nj.w[w], Ai), Aj, r[w]);   // (ni ^ nj) & Ai & Aj & r
     ni.w[w] ^= d[w];
     nj.w[w] ^= d[w];
   }
