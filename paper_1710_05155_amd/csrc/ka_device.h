@@ -33,6 +33,10 @@ constexpr uint32_t kTTMaj = ((0xF0u & 0xCCu) | (0xF0u & 0xAAu) | (0xCCu & 0xAAu)
 constexpr uint32_t kTTAnd3 = (0xF0u & 0xCCu & 0xAAu) & 0xFFu;                           // a & b & c
 constexpr uint32_t kTTXorAnd = ((0xF0u ^ 0xCCu) & 0xAAu) & 0xFFu;                       // (a ^ b) & c
 constexpr uint32_t kTTXorOfAnd = (0xF0u ^ (0xCCu & 0xAAu)) & 0xFFu;                     // a ^ (b & c)
+// one step of a bit-serial "greater than" from the low bit up: a = bit of x, b = bit of y (as
+// an all-ones / all-zeros mask), c = "the lower bits of x exceed those of y"
+constexpr uint32_t kTTGt = ((0xF0u & ~0xCCu) | (~(0xF0u ^ 0xCCu) & 0xAAu)) & 0xFFu;
+constexpr uint32_t kTTNotGt = ~kTTGt & 0xFFu;
 
 template <uint32_t TT>
 __device__ __forceinline__ uint32_t bit3(uint32_t a, uint32_t b, uint32_t c)
@@ -181,33 +185,33 @@ __device__ __forceinline__ void bitsum(const u64 (&x)[K], u64 &s0, u64 &s1, u64 
   }
 }
 
-// m is wave-uniform, so the branches below are scalar.
+// Per lane, sum (s2 s1 s0) <= m for a wave-uniform m in [0, 7]: a bit-serial comparison from
+// the low bit up with one three-input instruction per bit; the bits of m become all-ones /
+// all-zeros masks, which stay in scalar registers.  (Written with branches on m, the compiler
+// turned the comparison into selects, about eight instructions per 32-bit half.)
 __device__ __forceinline__ u64 at_most(u64 s0, u64 s1, u64 s2, int m)
 {
-  if (m >= 7) return ~0ull;
-  u64 gt = 0, eq = ~0ull;
-  if (m & 4) {
-    eq = s2;
-  } else {
-    gt = s2;
-    eq = ~s2;
-  }
-  if (m & 2) {
-    eq &= s1;
-  } else {
-    gt |= eq & s1;
-    eq &= ~s1;
-  }
-  if (!(m & 1)) gt |= eq & s0;
-  return ~gt;
+  const u64 m0 = (m & 1) ? ~0ull : 0ull, m1 = (m & 2) ? ~0ull : 0ull, m2 = (m & 4) ? ~0ull : 0ull;
+  const u64 g0 = s0 & ~m0;
+  const u64 g1 = bit3<kTTGt>(s1, m1, g0);
+  return bit3<kTTNotGt>(s2, m2, g1);
 }
 
+// The same for sums of at most three inputs (s2 = 0), where m <= 3.
+__device__ __forceinline__ u64 at_most2(u64 s0, u64 s1, int m)
+{
+  const u64 m0 = (m & 1) ? ~0ull : 0ull, m1 = (m & 2) ? ~0ull : 0ull;
+  return bit3<kTTNotGt>(s1, m1, s0 & ~m0);
+}
+
+// m <= z - 1 = K, so a sum of at most three inputs is compared with an m below 4.
 template <int K>
 __device__ __forceinline__ u64 activity(const u64 (&x)[K], int m)
 {
   u64 s0, s1, s2;
   bitsum<K>(x, s0, s1, s2);
-  return at_most(s0, s1, s2, m);
+  if constexpr (K <= 3) return at_most2(s0, s1, m);
+  else return at_most(s0, s1, s2, m);
 }
 
 // Exchange for one element pair; returns d per word.
