@@ -264,14 +264,16 @@ typedef struct ka_batch ka_batch;
 int ka_batch_create(int capacity, void *hip_stream, ka_batch **out);
 
 /* Add sim s to advance by n_sweeps sweeps, starting at the next step enqueued (or later,
- * under KA_BOPT_CACHE_BUDGET).  The sim
+ * under KA_BOPT_CACHE_BUDGET, or for a solo member behind the solo members added before
+ * it: see KA_BOPT_SOLO_BYTES).  The sim
  * must be on the batch's device and in no other batch; until it is detached (ka_batch_poll,
  * ka_batch_wait_all) every other call on it returns KA_ESTATE.  *slot receives its slot. */
 int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot);
 
 /* Enqueue n_steps steps (asynchronous).  Each step is one kernel launch per words-per-
- * thread variant present, one workgroup per tile of active work.  The first call tunes the
- * tile (workgroup) size on its first steps unless KA_BOPT_AUTOTUNE is 0. */
+ * thread variant present, one workgroup per tile of active work, and the running solo
+ * member's own class-pass launch.  The first call tunes the tile (workgroup) size on its
+ * first steps unless KA_BOPT_AUTOTUNE is 0. */
 int ka_batch_run(ka_batch *b, int64_t n_steps);
 
 /* Steps still to enqueue until every member's work is enqueued. */
@@ -292,12 +294,20 @@ int ka_batch_wait_all(ka_batch *b);
  * the budget next to the large members still running (or when none runs); otherwise it
  * waits, in the order added, and starts at the step where enough of them have finished.
  * Sized to the device's last-level cache (256 MiB Infinity Cache on MI355X), this keeps the
- * large members' state cache-resident between steps.  A member's result does not depend
- * on when it starts; ka_batch_steps_left counts the waiting members' steps too. */
+ * large members' state cache-resident between steps.  KA_BOPT_SOLO_BYTES (bytes, default
+ * 32 MiB; 0 = off; set while the batch has no members, else KA_ESTATE): members whose n and
+ * f take at least this many bytes fill the device with their own class passes, so they are
+ * solo members: they skip the step kernel, wait in the order added, and run one at a time,
+ * each step advancing the running one by one launch of the pass kernels ka_sweep uses (all
+ * word planes in each), which keeps its state in the Infinity Cache instead of sharing it
+ * with every other member's.  Cache-budget rules apply to the other members only.  A
+ * member's result does not depend on when it starts or how it runs; ka_batch_steps_left
+ * counts the waiting members' steps too. */
 #define KA_BOPT_AUTOTUNE 1
 #define KA_BOPT_BLOCK 2
 #define KA_BOPT_GRAPH_STEPS 4
 #define KA_BOPT_CACHE_BUDGET 5
+#define KA_BOPT_SOLO_BYTES 6
 int ka_batch_set_option(ka_batch *b, int option, int64_t value);
 
 /* Global step (enqueued), attached members, tile size in use, and tiles per step of the

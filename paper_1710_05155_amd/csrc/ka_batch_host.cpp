@@ -87,6 +87,16 @@ struct ka_batch {
   std::vector<int64_t> ws;               // per slot: bytes of n and f
   std::vector<char> waiting_flag;        // per slot: added but not started yet
   std::deque<int> waiting;               // slots in admission order
+  // One-at-a-time members (KA_BOPT_SOLO_BYTES): a member whose n and f take at least
+  // solo_bytes fills the device with its own class passes, and run next to other members'
+  // step kernels it would only push their state and its own out of the Infinity Cache.  Such
+  // members skip the step kernel: they queue in the order added and run one at a time, each
+  // step advancing the running one by one launch of its own pass kernels (ka_sim_passes) on
+  // the batch's stream, so that a step still advances every started member by one class.
+  int64_t solo_bytes = (int64_t)32 << 20;
+  std::vector<char> solo;                // per slot
+  std::deque<int> solo_waiting;          // solo slots not started yet, in admission order
+  int seg_solo = -1;                     // the solo member running in the current segment
   int n_members = 0;                     // highest used slot + 1
   int64_t step = 0;                      // steps enqueued
   int64_t done_step = 0;                 // steps known complete on the device
@@ -144,7 +154,17 @@ bool active_at(const ka_batch *b, int k, int64_t s)
 
 bool large_member(const ka_batch *b, int k)
 {
-  return b->cache_budget > 0 && b->ws[(size_t)k] * 8 >= b->cache_budget;
+  return b->cache_budget > 0 && !b->solo[(size_t)k] && b->ws[(size_t)k] * 8 >= b->cache_budget;
+}
+
+// Last step of the started solo member still running at step s (s itself when none runs).
+int64_t solo_busy_until(const ka_batch *b, int64_t s)
+{
+  int64_t until = s;
+  for (int k = 0; k < b->n_members; ++k)
+    if (b->sims[(size_t)k] && b->solo[(size_t)k] && !b->waiting_flag[(size_t)k])
+      until = std::max<int64_t>(until, b->tab[(size_t)k].s_end);
+  return until;
 }
 
 // Bytes of large started members that still run at or after step s.
@@ -174,7 +194,7 @@ void start_member(ka_batch *b, int k, int64_t s)
 }
 
 // Start waiting members, in order, that fit next to the large members running at the
-// current step.
+// current step, and the next solo member once none runs.
 void admit_waiting(ka_batch *b)
 {
   while (!b->waiting.empty()) {
@@ -182,6 +202,10 @@ void admit_waiting(ka_batch *b)
     if (!fits_budget(b, large_bytes_from(b, b->step), b->ws[(size_t)k])) break;
     b->waiting.pop_front();
     start_member(b, k, b->step);
+  }
+  if (!b->solo_waiting.empty() && solo_busy_until(b, b->step) == b->step) {
+    start_member(b, b->solo_waiting.front(), b->step);
+    b->solo_waiting.pop_front();
   }
 }
 
@@ -211,6 +235,12 @@ int64_t projected_end(const ka_batch *b)
     const int64_t e = s + (int64_t)b->tab[(size_t)k].C * b->sweeps[(size_t)k];
     large.emplace_back(e, b->ws[(size_t)k]);
     end = std::max(end, e);
+  }
+  // solo members one after another, the first when the running one ends
+  int64_t solo_at = solo_busy_until(b, b->step);
+  for (int k : b->solo_waiting) {
+    solo_at += (int64_t)b->tab[(size_t)k].C * b->sweeps[(size_t)k];
+    end = std::max(end, solo_at);
   }
   return end;
 }
@@ -247,7 +277,8 @@ hipError_t new_segment(ka_batch *b)
   hipError_t e = hipSuccess;
   if (b->dirty) {
     for (int k = 0; k < b->n_members; ++k)
-      if (b->sims[(size_t)k]) b->tab[(size_t)k].tiles_per_plane = tiles_per_plane(b, k, b->block);
+      if (b->sims[(size_t)k])
+        b->tab[(size_t)k].tiles_per_plane = b->solo[(size_t)k] ? 0 : tiles_per_plane(b, k, b->block);
     const int q = b->stage_next;
     e = hipEventSynchronize(b->stage_ev[q]);   // this copy's previous upload has been read
     if (e != hipSuccess) return e;
@@ -262,11 +293,13 @@ hipError_t new_segment(ka_batch *b)
   const int64_t S = b->step;
   int T[2] = {0, 0};
   int64_t end = INT64_MAX;
+  b->seg_solo = -1;
   for (int k = 0; k < b->n_members; ++k) {
     if (!active_at(b, k, S)) continue;
     const ka::BatchMember &m = b->tab[(size_t)k];
     T[m.wpt - 1] += m.planes * m.tiles_per_plane;
     end = std::min<int64_t>(end, m.s_end);
+    if (b->solo[(size_t)k]) b->seg_solo = k;
   }
   b->buf ^= 1;
   for (int w = 0; w < 2 && e == hipSuccess; ++w) {
@@ -319,6 +352,15 @@ hipError_t launch_graph(ka_batch *b)
   return hipGraphLaunch(g.x, b->stream);
 }
 
+// The running solo member's launches for steps [from, from + count) of the current segment,
+// which lies inside that member's steps.
+hipError_t solo_passes(ka_batch *b, int64_t from, int64_t count)
+{
+  const int k = b->seg_solo;
+  if (k < 0 || count <= 0) return hipSuccess;
+  return ka_sim_passes(b->sims[(size_t)k], from - b->tab[(size_t)k].s_begin, count, b->stream);
+}
+
 hipError_t enqueue_steps(ka_batch *b, int64_t n)
 {
   hipError_t e = hipSuccess;
@@ -330,9 +372,14 @@ hipError_t enqueue_steps(ka_batch *b, int64_t n)
     }
     int64_t chunk = std::min<int64_t>(n, b->seg_end - b->step);
     if (b->T[0] == 0 && b->T[1] == 0) {
-      e = ka::launch_batch_advance(b->d_base, (int)std::min<int64_t>(chunk, 1 << 30), b->stream);
+      // no step kernel in this segment: the device step base still moves by the whole chunk
+      for (int64_t left = chunk; left > 0 && e == hipSuccess; left -= 1 << 30)
+        e = ka::launch_batch_advance(b->d_base, (int)std::min<int64_t>(left, 1 << 30), b->stream);
+      if (e == hipSuccess) e = solo_passes(b, b->step, chunk);
     } else {
-      int64_t left = chunk;
+      // each run of step kernels is followed by the solo member's launches for the same
+      // steps (independent sims: their order does not matter)
+      int64_t left = chunk, at = b->step;
       while (e == hipSuccess && b->graph_steps > 0 && left >= b->graph_steps) {
         e = launch_graph(b);
         if (e != hipSuccess) {
@@ -342,12 +389,16 @@ hipError_t enqueue_steps(ka_batch *b, int64_t n)
           (void)hipGetLastError();
           e = launch_steps(b, b->graph_steps);
         }
+        if (e == hipSuccess) e = solo_passes(b, at, b->graph_steps);
         left -= b->graph_steps;
+        at += b->graph_steps;
       }
       while (e == hipSuccess && left > 0) {
         const int r = (int)std::min<int64_t>(left, 1024);
         e = launch_steps(b, r);
+        if (e == hipSuccess) e = solo_passes(b, at, r);
         left -= r;
+        at += r;
       }
     }
     b->step += chunk;
@@ -452,6 +503,7 @@ extern "C" int ka_batch_create(int capacity, void *hip_stream, ka_batch **out)
     b->class_sizes.assign((size_t)capacity, std::vector<int>());
     b->ws.assign((size_t)capacity, 0);
     b->waiting_flag.assign((size_t)capacity, 0);
+    b->solo.assign((size_t)capacity, 0);
     hipError_t e = hipSuccess;
     if (hip_stream) {
       b->stream = (hipStream_t)hip_stream;
@@ -525,9 +577,8 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
     m.N = (int)s->N;
     m.z = s->z;
     m.m = s->m;
-    m.C = s->C;
+    m.C = ka_sim_steps_per_sweep(s);   // below s->C when a graph's tiny tail is merged
     m.classes = s->C;
-    if (!s->lattice && s->tail_opt && s->tail_first < s->C) m.C = s->tail_first + 1;   // merged tail
     m.planes = s->planes;
     m.wpt = s->wpt;
     m.key0 = (uint32_t)s->seed;
@@ -541,8 +592,15 @@ extern "C" int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot)
     b->sims[(size_t)k] = s;
     b->sweeps[(size_t)k] = n_sweeps;
     b->ws[(size_t)k] = (int64_t)2 * s->N * s->W * 8;
+    b->solo[(size_t)k] = b->solo_bytes > 0 && b->ws[(size_t)k] >= b->solo_bytes;
     b->n_members = std::max(b->n_members, k + 1);
-    if (large_member(b, k) && (!b->waiting.empty() || !fits_budget(b, large_bytes_from(b, b->step), b->ws[(size_t)k]))) {
+    if (b->solo[(size_t)k] && (!b->solo_waiting.empty() || solo_busy_until(b, b->step) > b->step)) {
+      // runs when the solo members added before it have finished
+      b->tab[(size_t)k].s_begin = INT64_MAX;
+      b->tab[(size_t)k].s_end = INT64_MAX;
+      b->waiting_flag[(size_t)k] = 1;
+      b->solo_waiting.push_back(k);
+    } else if (large_member(b, k) && (!b->waiting.empty() || !fits_budget(b, large_bytes_from(b, b->step), b->ws[(size_t)k]))) {
       // waits until enough of the large members already running have finished
       b->tab[(size_t)k].s_begin = INT64_MAX;
       b->tab[(size_t)k].s_end = INT64_MAX;
@@ -643,6 +701,12 @@ extern "C" int ka_batch_set_option(ka_batch *b, int option, int64_t value)
         for (int k = 0; k < b->n_members; ++k)
           if (b->sims[(size_t)k]) return bfail(KA_ESTATE, "the cache budget is set while the batch has no members");
         b->cache_budget = value;
+        return KA_OK;
+      case KA_BOPT_SOLO_BYTES:
+        if (value < 0) return bfail(KA_EINVAL, "solo bytes must be >= 0");
+        for (int k = 0; k < b->n_members; ++k)
+          if (b->sims[(size_t)k]) return bfail(KA_ESTATE, "the solo threshold is set while the batch has no members");
+        b->solo_bytes = value;
         return KA_OK;
       default:
         return bfail(KA_EINVAL, "unknown batch option %d", option);

@@ -648,11 +648,15 @@ int plane_cache_words(int64_t N, int W)
 #endif
 constexpr int kRowTileLog2 = KA_ROW_TILE_LOG2;
 
-hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split, int c_end, int plane0 = 0, int nplanes = 0)
+// One class pass (classes c .. c_end - 1 of a general graph's merged tail in one launch) on
+// the sim's stream, or on `on` when given (then without per-launch timing events).
+hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split, int c_end, int plane0 = 0, int nplanes = 0,
+                        hipStream_t on = nullptr)
 {
   const uint32_t k0 = (uint32_t)s->seed, k1 = (uint32_t)(s->seed >> 32);
+  hipStream_t st = on ? on : s->stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  const bool timed = s->timing_every > 0 && (s->launches % s->timing_every) == 0;
+  const bool timed = !on && s->timing_every > 0 && (s->launches % s->timing_every) == 0;
   if (timed) {
     e0 = pooled_event(s);
     e1 = pooled_event(s);
@@ -696,7 +700,7 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split, int c_end, int
     }
     a.plane0 = plane0;
     if (nplanes > 0) a.planes = nplanes;   // one group of planes
-    err = ka::launch_pass_lattice(a, s->m, s->wpt, s->stream);
+    err = ka::launch_pass_lattice(a, s->m, s->wpt, st);
   } else {
     ka::PassGraph a{};
     a.n = s->n;
@@ -718,9 +722,9 @@ hipError_t launch_class(ka_sim *s, int c, uint32_t t, bool split, int c_end, int
     if (c_end > c + 1) {
       a.class_start = s->class_start_d;
       a.c_end = (uint32_t)c_end;
-      err = ka::launch_tail_graph(a, s->z, s->m, s->wpt, s->stream);
+      err = ka::launch_tail_graph(a, s->z, s->m, s->wpt, st);
     } else {
-      err = a.count > 0 ? ka::launch_pass_graph(a, s->z, s->m, s->wpt, s->stream) : hipSuccess;
+      err = a.count > 0 ? ka::launch_pass_graph(a, s->z, s->m, s->wpt, st) : hipSuccess;
     }
   }
   if (timed) {
@@ -1329,6 +1333,24 @@ extern "C" int ka_observe_noalloc(ka_sim *s, int64_t *t, int64_t *density, int64
     if (t) *t = s->t;
     return KA_OK;
   });
+}
+
+int ka_sim_steps_per_sweep(const ka_sim *s)
+{
+  return (!s->lattice && s->tail_opt && s->tail_first < s->C) ? s->tail_first + 1 : s->C;
+}
+
+hipError_t ka_sim_passes(ka_sim *s, int64_t p0, int64_t count, hipStream_t stream)
+{
+  const int per = ka_sim_steps_per_sweep(s);
+  hipError_t e = hipSuccess;
+  for (int64_t p = p0; p < p0 + count && e == hipSuccess; ++p) {
+    const uint32_t t = (uint32_t)(s->t + p / per);
+    const int c = (int)(p % per);
+    const int c_end = (per < s->C && c == per - 1) ? s->C : c + 1;   // the merged tail
+    e = launch_class(s, c, t, false, c_end, 0, 0, stream);
+  }
+  return e;
 }
 
 // Enqueue the counts of ka_observe at the current t on the sim's stream, copied into

@@ -110,6 +110,13 @@ struct ka_sim {
 void ka_set_error(const char *msg);
 // Finish the batch work of a member that is being freed.
 int ka_batch_release_member(ka_batch *b, ka_sim *s);
+// Launches per sweep of the sim's global path: its classes, with the merged run of tiny
+// trailing classes of a general graph counted as one.
+int ka_sim_steps_per_sweep(const ka_sim *s);
+// Launches p0 .. p0 + count - 1 of the sim's global path counted from sweep s->t (launch p:
+// step p mod P of sweep s->t + p / P, P = ka_sim_steps_per_sweep), every word plane in each,
+// on `stream`; s->t is left as it is.  A batch runs its one-at-a-time members with it.
+hipError_t ka_sim_passes(ka_sim *s, int64_t p0, int64_t count, hipStream_t stream);
 // Counts of ka_observe enqueued on the sim's stream into pinned host memory (3 * R values).
 int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out);
 // Move a sim onto a new stream that it owns (its old stream may then be destroyed).  With

@@ -59,6 +59,7 @@ KA_BOPT_AUTOTUNE = 1
 KA_BOPT_BLOCK = 2
 KA_BOPT_GRAPH_STEPS = 4
 KA_BOPT_CACHE_BUDGET = 5
+KA_BOPT_SOLO_BYTES = 6
 
 
 class KaError(RuntimeError):

@@ -154,12 +154,16 @@ def test_batch_members_match_oracle(oracle):
         assert np.array_equal(dens, od) and np.array_equal(ov, oo) and np.array_equal(pers, op)
 
 
-def test_members_added_while_running(graphs, solo):
+@pytest.mark.parametrize("solo_bytes", [None, 1 << 16])
+def test_members_added_while_running(graphs, solo, solo_bytes):
     """Continuous batching: members join after the batch has started and leave as they
-    finish; each still ends in its solo state."""
-    _say("batch: staggered admission")
+    finish; each still ends in its solo state (also with some members run one at a time,
+    solo members queueing behind each other as they join)."""
+    _say(f"batch: staggered admission, solo bytes {solo_bytes}")
     b = ka.ka_batch_create(8)  # fewer slots than members: slots are reused
     ka.ka_batch_set_option(b, ka.KA_BOPT_GRAPH_STEPS, 4)
+    if solo_bytes is not None:
+        ka.ka_batch_set_option(b, ka.KA_BOPT_SOLO_BYTES, solo_bytes)
     pending = list(range(len(MEMBERS)))
     sims = {}
     results = {}
@@ -299,14 +303,71 @@ def test_cache_budget_set_before_members(graphs):
     b = ka.ka_batch_create(4)
     s = _make(MEMBERS[0], graphs[0])
     ka.ka_batch_add(b, s, 1)
-    with pytest.raises(ka.KaError) as e:
-        ka.ka_batch_set_option(b, ka.KA_BOPT_CACHE_BUDGET, 1 << 20)
-    assert e.value.code == ka.KA_ESTATE
-    with pytest.raises(ka.KaError) as e:
-        ka.ka_batch_set_option(b, ka.KA_BOPT_CACHE_BUDGET, -1)
-    assert e.value.code == ka.KA_EINVAL
+    for opt in (ka.KA_BOPT_CACHE_BUDGET, ka.KA_BOPT_SOLO_BYTES):
+        with pytest.raises(ka.KaError) as e:
+            ka.ka_batch_set_option(b, opt, 1 << 20)
+        assert e.value.code == ka.KA_ESTATE
+        with pytest.raises(ka.KaError) as e:
+            ka.ka_batch_set_option(b, opt, -1)
+        assert e.value.code == ka.KA_EINVAL
     b.free()
     s.free()
+
+
+def _working_set(spec, g):
+    return 2 * g.N * (spec[5] // 64) * 8      # n and f
+
+
+# 64 KiB: the 2D L=64 x 64, 3D L=16 x 128 and RRG N=1000 x 320 members run one at a time;
+# 1 byte: every member does; 0: none does.
+@pytest.mark.parametrize("solo_bytes", [1 << 16, 1, 0])
+def test_solo_members_equal_solo(graphs, solo, solo_bytes):
+    """KA_BOPT_SOLO_BYTES: members whose n and f take at least that many bytes skip the step
+    kernel and run one at a time, in the order added, through their own pass kernels, one
+    launch per step.  ka_batch_steps_left projects that schedule exactly (the solo members'
+    steps add up, the others run from step 0), that many steps complete every member, and
+    each ends in its solo state."""
+    import time
+    _say(f"batch: solo bytes {solo_bytes}")
+    b = ka.ka_batch_create(64)
+    ka.ka_batch_set_option(b, ka.KA_BOPT_SOLO_BYTES, solo_bytes)
+    ka.ka_batch_set_option(b, ka.KA_BOPT_GRAPH_STEPS, 8)
+    sims, batched, solo_steps, n_solo = [], 0, 0, 0
+    for spec, g in zip(MEMBERS, graphs):
+        s = _make(spec, g)
+        if spec[0] == "rrg":
+            ka.ka_set_option(s, ka.KA_OPT_TAIL, 0)   # one step per class
+        ka.ka_batch_add(b, s, spec[7])
+        sims.append(s)
+        steps = g.C * spec[7]
+        if solo_bytes > 0 and _working_set(spec, g) >= solo_bytes:
+            solo_steps += steps
+            n_solo += 1
+        else:
+            batched = max(batched, steps)
+    assert n_solo == {1 << 16: 3, 1: len(MEMBERS), 0: 0}[solo_bytes]
+    left = ka.ka_batch_steps_left(b)
+    assert left == max(batched, solo_steps)
+    # in uneven chunks, so that runs of step kernels and solo launches end mid-sweep
+    chunks = [5, 17, 64, 3]
+    q = 0
+    while left > 0:
+        r = min(left, chunks[q % len(chunks)])
+        ka.ka_batch_run(b, r)
+        left -= r
+        q += 1
+    assert ka.ka_batch_steps_left(b) == 0
+    done = set()
+    deadline = time.time() + 60
+    while len(done) < len(MEMBERS):
+        assert time.time() < deadline, "members did not complete in the projected steps"
+        done.update(ka.ka_batch_poll(b))
+        time.sleep(0.001)
+    _assert_same([ka.ka_get_state(s) for s in sims], solo)
+    assert all(s.t == spec[7] for s, spec in zip(sims, MEMBERS))
+    b.free()
+    for s in sims:
+        s.free()
 
 
 TAIL_MEMBERS = [
@@ -330,13 +391,14 @@ def _tail_first(class_sizes, most=512):
     return c if C - c >= 2 else C
 
 
-@pytest.mark.parametrize("tail", [1, 0])
-def test_batch_merged_tail_classes(tail):
+@pytest.mark.parametrize("tail,all_solo", [(1, False), (0, False), (1, True)])
+def test_batch_merged_tail_classes(tail, all_solo):
     """A graph member whose colouring ends in tiny classes runs that trailing run as one step
     (one workgroup per plane takes the classes in order), unless KA_OPT_TAIL is 0 on the sim;
     the projected steps count the run once, and either way every member ends in its solo
-    state."""
-    _say(f"batch: merged tail classes, tail={tail}")
+    state.  With every member run one at a time (KA_BOPT_SOLO_BYTES = 1) the merged run is one
+    launch of the member's own tail kernel, and the steps add up."""
+    _say(f"batch: merged tail classes, tail={tail}, all solo={all_solo}")
     graphs = [_graph(spec) for spec in TAIL_MEMBERS]
     solo = []
     for spec, g in zip(TAIL_MEMBERS, graphs):
@@ -345,6 +407,8 @@ def test_batch_merged_tail_classes(tail):
         solo.append(ka.ka_get_state(s))
         s.free()
     b = ka.ka_batch_create(8)
+    if all_solo:
+        ka.ka_batch_set_option(b, ka.KA_BOPT_SOLO_BYTES, 1)
     sims, expected = [], 0
     for spec, g in zip(TAIL_MEMBERS, graphs):
         s = _make(spec, g)
@@ -357,7 +421,10 @@ def test_batch_merged_tail_classes(tail):
             first = _tail_first(np.bincount(ec, minlength=g.C))
             assert first <= g.C - 2
             steps_per_sweep = first + 1
-        expected = max(expected, steps_per_sweep * spec[7])
+        if all_solo:
+            expected += steps_per_sweep * spec[7]
+        else:
+            expected = max(expected, steps_per_sweep * spec[7])
     assert ka.ka_batch_steps_left(b) == expected
     ka.ka_batch_wait_all(b)
     for k, (s, ref) in enumerate(zip(sims, solo)):
