@@ -211,10 +211,12 @@ def hbm_regime_measure(stream, jobs=2):
                          "traffic_source": "profiles/k_pass_lattice_cubic256.counters.txt" if traffic else None}}
 
 
-def batch_measure(steps, warmup, sweeps=1000, serial=True):
-    """256 uneven instances advanced together by the batched step kernel (timed `steps`
-    times after `warmup` untimed runs), against the same jobs run one at a time with the
-    single-instance path (once).  Returns a dict."""
+def batch_measure(steps, warmup, sweeps=1000, serial=True, solo_bytes=32 << 20):
+    """256 uneven instances advanced together by one batch (timed `steps` times after
+    `warmup` untimed runs), against the same jobs run one at a time with the single-instance
+    path (once).  Members whose n and f take at least solo_bytes (the 3D L=128 ones) run one
+    at a time inside the batch through their own pass kernels (KA_BOPT_SOLO_BYTES; 0: every
+    member in the step kernel).  Returns a dict."""
     import torch
     from paper_1710_05155_amd import ka, workloads
 
@@ -237,6 +239,7 @@ def batch_measure(steps, warmup, sweeps=1000, serial=True):
             adj, eu, ev, ec = ka.ka_graph_export(g)
             bytes_per_sweep[key] = graph_bytes_model(adj, eu, ev, ec, g.C, g.z, inst["R"] // 64)
     log(f"batch: built {len(graphs)} graphs in {time.perf_counter() - t0:.1f} s")
+    n_solo = sum(1 for i in man if solo_bytes > 0 and 2 * graphs[i["key"]].N * (i["R"] // 64) * 8 >= solo_bytes)
     attempts = sum(graphs[i["key"]].N * i["R"] * i["sweeps"] for i in man)
     model_bytes = sum(bytes_per_sweep[i["key"]] * i["sweeps"] for i in man)
 
@@ -250,6 +253,7 @@ def batch_measure(steps, warmup, sweeps=1000, serial=True):
         sims = [ka.ka_init(graphs[i["key"]], i["m"], i["rho"], i["seed"], i["R"],
                            stream=init_streams[k % len(init_streams)]) for k, i in enumerate(man)]
         b = ka.ka_batch_create(len(sims), stream=stream)
+        ka.ka_batch_set_option(b, ka.KA_BOPT_SOLO_BYTES, solo_bytes)
         if shape:
             ka.ka_batch_set_option(b, ka.KA_BOPT_BLOCK, shape["block"])
         for s, i in zip(sims, man):
@@ -299,10 +303,14 @@ def batch_measure(steps, warmup, sweeps=1000, serial=True):
     out = {"value": attempts * steps / wall, "unit": "site-replica move attempts/s",
            "ms_per_batch": wall * 1000.0 / steps, "instances": len(man), "sweeps_each": sweeps,
            "sites_total": int(sum(graphs[i["key"]].N for i in man)), "launch_shape": dict(shape),
+           "solo_bytes": solo_bytes, "solo_members": n_solo,
+           # one batch step: the step kernel over the batched members and one launch of the
+           # running solo member's pass kernel, whichever are present
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch_step",
-                        "avg_launch_us": ms * 1000.0 / launches,
-                        "bytes_per_launch": model_bytes / (launches / steps),
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "kernel": "k_batch_step and the solo members' k_pass_lattice",
+                        "steps_per_batch": launches // steps, "avg_step_us": ms * 1000.0 / launches,
+                        "bytes_per_step": model_bytes / (launches / steps), "kernel_ms_per_batch": ms / steps,
                         "byte_model": "12 B per site-word per lattice class pass; graph members as bench.graph_bytes_model"}}
     if serial:
         log("batch: one-at-a-time baseline ...")
@@ -318,7 +326,8 @@ def batch_measure(steps, warmup, sweeps=1000, serial=True):
 
 def run_batch_workload(args):
     """The batched workload as the bench line."""
-    r = batch_measure(args.steps, args.warmup, sweeps=args.sweeps or 1000, serial=not args.no_serial)
+    r = batch_measure(args.steps, args.warmup, sweeps=args.sweeps or 1000, serial=not args.no_serial,
+                      solo_bytes=args.solo_bytes)
     result = {
         "metric": "site-replica move attempts/s (1 GPU)",
         "value": r["value"],
@@ -328,8 +337,10 @@ def run_batch_workload(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": "256 uneven instances (2D L 32-512, 3D L 16-128, RRG N 2^12-2^18 z 3-5, "
                                f"m 1..z-1, rho U[0.5,0.9], 64 replicas), {r['sweeps_each']} sweeps each, batched "
-                               "step kernel in captured graphs, autotuned launch shape",
-                   "instances": r["instances"], "sites_total": r["sites_total"], "launch_shape": r["launch_shape"]},
+                               "step kernel in captured graphs, autotuned launch shape; members whose n and f take "
+                               f"at least {r['solo_bytes']} bytes run one at a time through their own pass kernels",
+                   "instances": r["instances"], "sites_total": r["sites_total"], "launch_shape": r["launch_shape"],
+                   "solo_members": r["solo_members"]},
         "roofline": r["roofline"],
     }
     for k in ("one_at_a_time", "speedup_vs_one_at_a_time"):
@@ -488,6 +499,9 @@ def main():
                     help="lattice workloads: run the word planes on two streams of each sim's own "
                          "(KA_OPT_PLANE_STREAMS=1) instead of one launch per class pass")
     ap.add_argument("--no-serial", action="store_true", help="batch workload: skip the one-at-a-time baseline")
+    ap.add_argument("--solo-bytes", type=int, default=32 << 20,
+                    help="batch workload: KA_BOPT_SOLO_BYTES (members whose n and f take at least this many "
+                         "bytes run one at a time inside the batch; 0: all in the step kernel)")
     ap.add_argument("--no-extras", action="store_true",
                     help="cubic128: skip the batch256 and serve figures after the headline")
     ap.add_argument("--replicas", type=int, default=None, help="override the replica count (exploration only)")
@@ -726,8 +740,10 @@ def main():
             "value": b["value"], "unit": b["unit"], "ms_per_batch": b["ms_per_batch"],
             "one_at_a_time_value": b["one_at_a_time"]["value"], "one_at_a_time_ms": b["one_at_a_time"]["ms"],
             "speedup_vs_one_at_a_time": b["speedup_vs_one_at_a_time"], "launch_shape": b["launch_shape"],
+            "solo_members": b["solo_members"],
             "config": "256 uneven instances (2D L 32-512, 3D L 16-128, RRG N 2^12-2^18 z 3-5), 64 replicas, "
-                      "1000 sweeps each; 1 warm-up batch, 1 timed"}
+                      f"1000 sweeps each; the {b['solo_members']} whose n and f take 32 MiB or more run one at a "
+                      "time inside the batch; 1 warm-up batch, 1 timed"}
         log(f"extra: serving trace of {args.jobs} jobs ...")
         sv = serve_measure(args.jobs, args.rate)
         result["serve"] = {
