@@ -203,7 +203,8 @@ void admit_waiting(ka_batch *b)
     b->waiting.pop_front();
     start_member(b, k, b->step);
   }
-  if (!b->solo_waiting.empty() && solo_busy_until(b, b->step) == b->step) {
+  // (a member with no sweeps ends where it starts, and the next one starts with it)
+  while (!b->solo_waiting.empty() && solo_busy_until(b, b->step) == b->step) {
     start_member(b, b->solo_waiting.front(), b->step);
     b->solo_waiting.pop_front();
   }

@@ -391,6 +391,36 @@ def _tail_first(class_sizes, most=512):
     return c if C - c >= 2 else C
 
 
+def test_solo_members_with_no_sweeps():
+    """Solo members queued behind one with no sweeps still start: the one with no sweeps ends
+    at the step it starts, and the next starts there too."""
+    _say("batch: solo members with zero sweeps in the queue")
+    g = ka.ka_graph_lattice(2, 16)
+    plan = [(1, 2), (2, 0), (3, 0), (4, 3)]      # (seed, sweeps)
+    ref = []
+    for seed, n in plan:
+        s = ka.ka_init(g, 2, 0.6, seed, 64)
+        ka.ka_sweep(s, n)
+        ref.append(ka.ka_get_state(s))
+        s.free()
+    b = ka.ka_batch_create(8)
+    ka.ka_batch_set_option(b, ka.KA_BOPT_SOLO_BYTES, 1)
+    sims = []
+    for seed, n in plan:
+        s = ka.ka_init(g, 2, 0.6, seed, 64)
+        ka.ka_batch_add(b, s, n)
+        sims.append(s)
+    assert ka.ka_batch_steps_left(b) == g.C * 5
+    ka.ka_batch_wait_all(b)
+    for k, (s, r) in enumerate(zip(sims, ref)):
+        assert s.t == plan[k][1]
+        for x, y in zip(ka.ka_get_state(s), r):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), k
+    b.free()
+    for s in sims:
+        s.free()
+
+
 @pytest.mark.parametrize("tail,all_solo", [(1, False), (0, False), (1, True)])
 def test_batch_merged_tail_classes(tail, all_solo):
     """A graph member whose colouring ends in tiny classes runs that trailing run as one step
