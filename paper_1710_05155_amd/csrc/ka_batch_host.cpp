@@ -88,11 +88,12 @@ struct ka_batch {
   std::vector<char> waiting_flag;        // per slot: added but not started yet
   std::deque<int> waiting;               // slots in admission order
   // One-at-a-time members (KA_BOPT_SOLO_BYTES): a member whose n and f take at least
-  // solo_bytes fills the device with its own class passes, and run next to other members'
-  // step kernels it would only push their state and its own out of the Infinity Cache.  Such
-  // members skip the step kernel: they queue in the order added and run one at a time, each
-  // step advancing the running one by one launch of its own pass kernels (ka_sim_passes) on
-  // the batch's stream, so that a step still advances every started member by one class.
+  // solo_bytes fills the device with its own class passes; run inside the step kernels next
+  // to other members, it would only push their state and its own out of the Infinity Cache.
+  // Such members skip the step kernel: they queue in the order added and run one at a time,
+  // each step advancing the running one by one launch of its own pass kernels
+  // (ka_sim_passes) on the batch's stream, so that a step still advances every started member
+  // by one class.
   int64_t solo_bytes = (int64_t)32 << 20;
   std::vector<char> solo;                // per slot
   std::deque<int> solo_waiting;          // solo slots not started yet, in admission order
