@@ -272,8 +272,8 @@ int ka_batch_add(ka_batch *b, ka_sim *s, int64_t n_sweeps, int *slot);
 
 /* Enqueue n_steps steps (asynchronous).  Each step is one kernel launch per words-per-
  * thread variant present, one workgroup per tile of active work, and the running solo
- * member's own class-pass launch.  The first call tunes the tile (workgroup) size on its
- * first steps unless KA_BOPT_AUTOTUNE is 0. */
+ * member's own class pass.  The first call tunes the tile (workgroup) size on its first
+ * steps unless KA_BOPT_AUTOTUNE is 0. */
 int ka_batch_run(ka_batch *b, int64_t n_steps);
 
 /* Steps still to enqueue until every member's work is enqueued. */
@@ -298,9 +298,10 @@ int ka_batch_wait_all(ka_batch *b);
  * 32 MiB; 0 = off; set while the batch has no members, else KA_ESTATE): members whose n and
  * f take at least this many bytes fill the device with their own class passes, so they are
  * solo members: they skip the step kernel, wait in the order added, and run one at a time,
- * each step advancing the running one by one launch of the pass kernels ka_sweep uses (all
- * word planes in each), which keeps its state in the Infinity Cache instead of sharing it
- * with every other member's.  Cache-budget rules apply to the other members only.  A
+ * each step advancing the running one by one class pass through the pass kernels ka_sweep
+ * uses (in its groups of word planes, each group through a run of steps before the next),
+ * which keeps its state in the Infinity Cache instead of sharing it with every other
+ * member's.  Cache-budget rules apply to the other members only.  A
  * member's result does not depend on when it starts or how it runs; ka_batch_steps_left
  * counts the waiting members' steps too. */
 #define KA_BOPT_AUTOTUNE 1

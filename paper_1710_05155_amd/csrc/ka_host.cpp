@@ -1343,12 +1343,19 @@ int ka_sim_steps_per_sweep(const ka_sim *s)
 hipError_t ka_sim_passes(ka_sim *s, int64_t p0, int64_t count, hipStream_t stream)
 {
   const int per = ka_sim_steps_per_sweep(s);
+  // word planes in the groups ka_sweep uses, each group through all `count` launches before
+  // the next (the planes are independent chains)
+  const int group = s->plane_group_opt >= 0 ? s->plane_group_opt : s->plane_group;
+  const bool grouped = group > 0 && group < s->planes;
   hipError_t e = hipSuccess;
-  for (int64_t p = p0; p < p0 + count && e == hipSuccess; ++p) {
-    const uint32_t t = (uint32_t)(s->t + p / per);
-    const int c = (int)(p % per);
-    const int c_end = (per < s->C && c == per - 1) ? s->C : c + 1;   // the merged tail
-    e = launch_class(s, c, t, false, c_end, 0, 0, stream);
+  for (int q0 = 0; q0 < (grouped ? s->planes : 1) && e == hipSuccess; q0 += (grouped ? group : 1)) {
+    const int np = grouped ? std::min(group, s->planes - q0) : 0;
+    for (int64_t p = p0; p < p0 + count && e == hipSuccess; ++p) {
+      const uint32_t t = (uint32_t)(s->t + p / per);
+      const int c = (int)(p % per);
+      const int c_end = (per < s->C && c == per - 1) ? s->C : c + 1;   // the merged tail
+      e = launch_class(s, c, t, false, c_end, q0, np, stream);
+    }
   }
   return e;
 }

@@ -114,8 +114,9 @@ int ka_batch_release_member(ka_batch *b, ka_sim *s);
 // trailing classes of a general graph counted as one.
 int ka_sim_steps_per_sweep(const ka_sim *s);
 // Launches p0 .. p0 + count - 1 of the sim's global path counted from sweep s->t (launch p:
-// step p mod P of sweep s->t + p / P, P = ka_sim_steps_per_sweep), every word plane in each,
-// on `stream`; s->t is left as it is.  A batch runs its one-at-a-time members with it.
+// step p mod P of sweep s->t + p / P, P = ka_sim_steps_per_sweep), on `stream`, with the word
+// planes in the sim's groups as ka_sweep runs them (each group through all `count` launches
+// before the next); s->t is left as it is.  A batch runs its one-at-a-time members with it.
 hipError_t ka_sim_passes(ka_sim *s, int64_t p0, int64_t count, hipStream_t stream);
 // Counts of ka_observe enqueued on the sim's stream into pinned host memory (3 * R values).
 int ka_sim_observe_async(ka_sim *s, unsigned long long *host_out);

@@ -391,6 +391,57 @@ def _tail_first(class_sizes, most=512):
     return c if C - c >= 2 else C
 
 
+def test_solo_members_in_plane_groups():
+    """A solo member whose word planes run in groups (KA_OPT_PLANE_GROUPS, as ka_sweep does
+    for lattices beyond the Infinity Cache) advances group by group through each run of steps;
+    lattices with word pairs and single words and a graph whose whole sweep is one merged
+    launch, next to a member in the step kernel, all end in their solo states."""
+    import time
+    _say("batch: solo members in plane groups")
+    specs = [  # graph, m, rho, R, seed, sweeps, planes per group
+        (ka.ka_graph_lattice(2, 64), 2, 0.7, 256, 61, 3, 1),      # 2 planes of word pairs
+        (ka.ka_graph_lattice(3, 16), 3, 0.85, 192, 62, 2, 2),     # 3 planes: groups of 2 and 1
+        (ka.ka_graph_rrg(2000, 4, 63), 2, 0.65, 192, 63, 4, 2),   # every class small: one launch per sweep
+        (ka.ka_graph_lattice(2, 8), 2, 0.6, 64, 64, 9, -1),       # 1 KiB: in the step kernel
+    ]
+    ref = []
+    for g, m, rho, R, seed, n, grp in specs:
+        s = ka.ka_init(g, m, rho, seed, R)
+        ka.ka_set_option(s, ka.KA_OPT_PLANE_GROUPS, grp)
+        ka.ka_sweep(s, n)
+        ref.append(ka.ka_get_state(s))
+        s.free()
+    b = ka.ka_batch_create(8)
+    ka.ka_batch_set_option(b, ka.KA_BOPT_SOLO_BYTES, 64 << 10)
+    ka.ka_batch_set_option(b, ka.KA_BOPT_GRAPH_STEPS, 8)
+    sims = []
+    for g, m, rho, R, seed, n, grp in specs:
+        s = ka.ka_init(g, m, rho, seed, R)
+        ka.ka_set_option(s, ka.KA_OPT_PLANE_GROUPS, grp)
+        ka.ka_batch_add(b, s, n)
+        sims.append(s)
+    left = ka.ka_batch_steps_left(b)
+    chunks = [7, 30, 2, 64]
+    q = 0
+    while left > 0:
+        r = min(left, chunks[q % len(chunks)])
+        ka.ka_batch_run(b, r)
+        left -= r
+        q += 1
+    done = set()
+    deadline = time.time() + 60
+    while len(done) < len(specs):
+        assert time.time() < deadline, "members did not complete in the projected steps"
+        done.update(ka.ka_batch_poll(b))
+        time.sleep(0.001)
+    for k, (s, r) in enumerate(zip(sims, ref)):
+        for x, y in zip(ka.ka_get_state(s), r):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), k
+    b.free()
+    for s in sims:
+        s.free()
+
+
 def test_solo_members_with_no_sweeps():
     """Solo members queued behind one with no sweeps still start: the one with no sweeps ends
     at the step it starts, and the next starts there too."""
