@@ -251,11 +251,13 @@ void ka_free(ka_sim *s);
 
 /* ------------------------------------------------------------------------------------ */
 /* Batches: many sims advanced together.  One step kernel applies one class pass to every */
-/* active member; member k, added at global step s_k with n_k sweeps, runs class          */
-/* (s - s_k) mod C_k of its sweep t_k + (s - s_k) / C_k at step s, for s_k <= s <          */
-/* s_k + C_k*n_k.  The per-edge arithmetic and random counters are those of ka_sweep, so   */
-/* a member ends in exactly the state ka_sweep(n_k) would give it alone.  Steps advance on */
-/* the device, so the library replays a captured HIP graph of step kernels.               */
+/* active member (a solo member, see KA_BOPT_SOLO_BYTES, takes its pass through its own   */
+/* kernels in the same step); member k, added at global step s_k with n_k sweeps, runs    */
+/* class (s - s_k) mod C_k of its sweep t_k + (s - s_k) / C_k at step s, for              */
+/* s_k <= s < s_k + C_k*n_k.  The per-edge arithmetic and random counters are those of    */
+/* ka_sweep, so a member ends in exactly the state ka_sweep(n_k) would give it alone.     */
+/* Steps advance on the device, so the library replays a captured HIP graph of step       */
+/* kernels.                                                                               */
 /* ------------------------------------------------------------------------------------ */
 typedef struct ka_batch ka_batch;
 
