@@ -220,3 +220,38 @@ def test_take_and_release_while_others_run(graphs):
         _, solo_state = _solo(graphs[key], m, rho, R, seed, sweeps + 2, None)
         for a, b in zip(state, solo_state):
             assert np.array_equal(np.asarray(a), np.asarray(b)), k
+
+
+SOLO_JOBS = [
+    # 3D L=128 x 64 replicas: n and f take 32 MiB, so the server's batch runs these two one at
+    # a time through their own passes (the default KA_BOPT_SOLO_BYTES) next to the small jobs
+    (("lat", 3, 128), 3, 0.85, 64, 21, 6, [0, 2, 6]),
+    (("lat", 2, 16), 1, 0.5, 128, 22, 20, [5, 20]),
+    (("lat", 3, 128), 3, 0.80, 64, 23, 4, [1, 4]),
+    (("rrg", 300, 4), 2, 0.65, 64, 24, 15, [7, 15]),
+]
+
+
+def test_served_solo_jobs_equal_solo():
+    """Jobs large enough to fill the device alone are solo members of the server's batch:
+    each job's observations and final state still equal its run alone."""
+    _say("serve: jobs run one at a time inside the server's batch")
+    graphs = {}
+    for key, *_ in SOLO_JOBS:
+        if key not in graphs:
+            graphs[key] = ka.ka_graph_lattice(key[1], key[2]) if key[0] == "lat" else ka.ka_graph_rrg(key[1], key[2], 40 + key[1])
+    sv = ka.ka_server_create(1 << 34, 8)
+    ids = [ka.ka_server_submit(sv, graphs[key], m, rho, seed, R, sweeps, obs_times=obs, keep_sim=True)
+           for (key, m, rho, R, seed, sweeps, obs) in SOLO_JOBS]
+    ka.ka_server_wait_idle(sv)
+    for jid, (key, m, rho, R, seed, sweeps, obs) in zip(ids, SOLO_JOBS):
+        res = ka.ka_server_result(sv, jid)
+        sim = ka.ka_server_take_sim(sv, jid)
+        state = ka.ka_get_state(sim)
+        sim.free()
+        (dens, ov, pers), ref = _solo(graphs[key], m, rho, R, seed, sweeps, obs)
+        assert np.array_equal(res["density"], dens) and np.array_equal(res["overlap"], ov), key
+        assert np.array_equal(res["persistence"], pers), key
+        for x, y in zip(state, ref):
+            assert np.array_equal(np.asarray(x), np.asarray(y)), key
+    sv.free()
