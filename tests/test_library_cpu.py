@@ -24,6 +24,19 @@ def test_header_symbols_exported():
         assert hasattr(lib, name), name
 
 
+def test_binding_constants_match_header():
+    """Every error code and option number the header defines has the same value in the
+    binding, and the binding defines no KA_ constant the header lacks."""
+    with open(os.path.join(ROOT, "include", "ka.h")) as fh:
+        header = fh.read()
+    defined = {name: int(val) for name, val in
+               re.findall(r"^#define (KA_[A-Z0-9_]+) \(?(-?\d+)\)?", header, flags=re.M)}
+    assert {"KA_OK", "KA_ESTATE", "KA_OPT_PLANE_GROUPS", "KA_BOPT_SOLO_BYTES"} <= set(defined)
+    bound = {name: getattr(ka, name) for name in dir(ka)
+             if re.fullmatch(r"KA_(E[A-Z]+|OK|OPT_[A-Z_]+|BOPT_[A-Z_]+)", name)}
+    assert bound == defined
+
+
 @pytest.mark.parametrize("d,L", [(2, 4), (2, 12), (2, 64), (3, 4), (3, 8), (3, 20)])
 def test_lattice_graph_matches_oracle(oracle, d, L):
     g = ka.ka_graph_lattice(d, L)
